@@ -1,0 +1,355 @@
+"""Seeded synthetic inputs: meshes, initial fields and case parameters.
+
+This module serves both the HIP library and the CPU oracle, so it holds none
+of the method's arithmetic: it only places mesh nodes, numbers them, tags wall
+faces and evaluates initial and analytic fields. Each side builds its own
+quadrature, derivative, lattice and filter tables from these inputs.
+
+Mesh nodes are placed at the Gauss-Lobatto-Legendre points returned by
+``numpy.polynomial.legendre`` (the roots of P_N' plus the end points); the
+solver treats whatever nodes it is given as the isoparametric map.
+
+Conventions (the public interface states them too): node index
+``i + (N+1) j + (N+1)^2 k`` with r fastest; ``xyz[E][np][dim]``;
+``gid[E][np]`` global node ids in ``[0, E*np)``, copies of a shared or
+periodic node carry the same id; ``face_tag[E][2 dim]`` over faces
+``(r-, r+, s-, s+, t-, t+)``, 0 = interior or periodic, k >= 1 = wall k whose
+velocity is ``wall_u[k-1]``. Lattice units: speed 1, c_s^2 = 1/3.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Callable, Optional
+
+import numpy as np
+
+CS2 = 1.0 / 3.0
+CS = math.sqrt(CS2)
+
+
+def gll_points(N: int) -> np.ndarray:
+    """GLL points on [-1, 1] from numpy's Legendre module (mesh placement only)."""
+    from numpy.polynomial import legendre as npleg
+
+    c = np.zeros(N + 1)
+    c[N] = 1.0
+    inner = np.sort(np.real(npleg.legroots(npleg.legder(c)))) if N >= 2 else np.zeros(0)
+    return np.concatenate([[-1.0], inner, [1.0]])
+
+
+@dataclass
+class Mesh:
+    dim: int
+    N: int
+    xyz: np.ndarray       # [E][np][dim]
+    gid: np.ndarray       # [E][np] int64
+    face_tag: np.ndarray  # [E][2dim] int32
+    wall_u: np.ndarray    # [ntags][dim]
+
+    @property
+    def E(self) -> int:
+        return int(self.xyz.shape[0])
+
+    @property
+    def np_(self) -> int:
+        return (self.N + 1) ** self.dim
+
+
+def box_mesh(dim: int, N: int, nel, lo, hi, periodic, wall_tags=None, wall_u=None,
+             warp: Optional[Callable[[np.ndarray], np.ndarray]] = None) -> Mesh:
+    """Structured box of nel[0] x nel[1] (x nel[2]) elements, elements ordered
+    with x fastest. ``wall_tags[m] = (tag_lo, tag_hi)`` for non-periodic
+    directions. ``warp`` maps node coordinates [..., dim] to displaced ones
+    (it must keep periodic copies consistent and walls in place)."""
+    nel = tuple(int(n) for n in nel)
+    lo = np.asarray(lo, dtype=float)
+    hi = np.asarray(hi, dtype=float)
+    n1 = N + 1
+    ref = (gll_points(N) + 1.0) / 2.0
+    h = (hi - lo) / np.asarray(nel, dtype=float)
+    E = int(np.prod(nel))
+    npn = n1 ** dim
+    # element multi-index (x fastest) and node multi-index (r fastest)
+    eidx = np.stack(np.unravel_index(np.arange(E), nel[::-1])[::-1], axis=1)      # [E][dim]
+    nidx = np.stack(np.unravel_index(np.arange(npn), (n1,) * dim)[::-1], axis=1)  # [np][dim]
+    xyz = np.zeros((E, npn, dim))
+    gcoord = np.zeros((E, npn, dim), dtype=np.int64)
+    gsize = []
+    for m in range(dim):
+        xyz[:, :, m] = lo[m] + (eidx[:, None, m] + ref[nidx[None, :, m]]) * h[m]
+        Gm = nel[m] * N + (0 if periodic[m] else 1)
+        gsize.append(Gm)
+        gcoord[:, :, m] = (eidx[:, None, m] * N + nidx[None, :, m]) % Gm
+    gid = np.zeros((E, npn), dtype=np.int64)
+    stride = 1
+    for m in range(dim):
+        gid += gcoord[:, :, m] * stride
+        stride *= gsize[m]
+    if warp is not None:
+        xyz = warp(xyz)
+    face_tag = np.zeros((E, 2 * dim), dtype=np.int32)
+    for m in range(dim):
+        if periodic[m]:
+            continue
+        tl, th = wall_tags[m]
+        face_tag[eidx[:, m] == 0, 2 * m] = tl
+        face_tag[eidx[:, m] == nel[m] - 1, 2 * m + 1] = th
+    ntags = int(face_tag.max()) if face_tag.size else 0
+    wu = np.zeros((max(ntags, 0), dim))
+    if wall_u is not None:
+        wu[:] = np.asarray(wall_u, dtype=float).reshape(-1, dim)[:ntags]
+    return Mesh(dim, N, xyz, gid, face_tag, wu)
+
+
+def min_node_spacing(mesh: Mesh) -> float:
+    """Smallest distance between neighbouring nodes along a reference line."""
+    n1 = mesh.N + 1
+    x = mesh.xyz.reshape((mesh.E,) + (n1,) * mesh.dim + (mesh.dim,))
+    hmin = np.inf
+    for m in range(mesh.dim):
+        ax = mesh.dim - m  # r is the last spatial axis of the reshaped array
+        dx = np.diff(x, axis=ax)
+        hmin = min(hmin, float(np.sqrt((dx ** 2).sum(-1)).min()))
+    return hmin
+
+
+# ----------------------------------------------------------------------------
+# Initial fields
+# ----------------------------------------------------------------------------
+
+def tgv2d_fields(xyz, u0, rho0=1.0, L0=1.0, t=0.0, nu=0.0):
+    """2D Taylor-Green vortex: u = u0 e^{-2 nu t / L0^2}(sin x cos y, -cos x sin y),
+    p = rho0 u0^2/4 (cos 2x + cos 2y) e^{-4 nu t}, rho = rho0 + p / c_s^2."""
+    x = xyz[..., 0] / L0
+    y = xyz[..., 1] / L0
+    a = math.exp(-2.0 * nu * t / (L0 * L0))
+    u = np.stack([u0 * a * np.sin(x) * np.cos(y), -u0 * a * np.cos(x) * np.sin(y)], axis=-1)
+    p = rho0 * u0 * u0 / 4.0 * (np.cos(2 * x) + np.cos(2 * y)) * a * a
+    return rho0 + p / CS2, u
+
+
+def tgv3d_fields(xyz, u0, rho0=1.0, L0=1.0):
+    """3D Taylor-Green vortex initial field, p = rho0 u0^2/16 (cos 2x + cos 2y)(cos 2z + 2)."""
+    x, y, z = (xyz[..., k] / L0 for k in range(3))
+    u = np.stack([u0 * np.sin(x) * np.cos(y) * np.cos(z),
+                  -u0 * np.cos(x) * np.sin(y) * np.cos(z),
+                  np.zeros_like(x)], axis=-1)
+    p = rho0 * u0 * u0 / 16.0 * (np.cos(2 * x) + np.cos(2 * y)) * (np.cos(2 * z) + 2.0)
+    return rho0 + p / CS2, u
+
+
+def double_shear_fields(xyz, u0, kappa=80.0, delta=0.05, rho0=1.0):
+    """Double shear layer on the unit square; the transverse perturbation is
+    delta * u0 * sin(2 pi (x + 1/4))."""
+    x = xyz[..., 0]
+    y = xyz[..., 1]
+    ux = np.where(y <= 0.5, u0 * np.tanh(kappa * (y - 0.25)), u0 * np.tanh(kappa * (0.75 - y)))
+    uy = delta * u0 * np.sin(2 * np.pi * (x + 0.25))
+    return np.full(x.shape, rho0), np.stack([ux, uy], axis=-1)
+
+
+def rest_fields(xyz, rho0=1.0):
+    dim = xyz.shape[-1]
+    return np.full(xyz.shape[:-1], rho0), np.zeros(xyz.shape)
+
+
+# ----------------------------------------------------------------------------
+# Analytic references
+# ----------------------------------------------------------------------------
+
+def couette_profile(y, t, U, H, nu, nterms=400):
+    """Start-up Couette flow between a wall at y = 0 and a plate at y = H moving at U."""
+    y = np.asarray(y, dtype=float)
+    u = U * y / H
+    for n in range(1, nterms + 1):
+        u = u - (2.0 * U / math.pi) * ((-1) ** (n + 1) / n) * np.sin(n * math.pi * y / H) * \
+            math.exp(-n * n * math.pi * math.pi * nu * t / (H * H))
+    return u
+
+
+def poiseuille_profile(y, t, g, H, nu, nterms=400):
+    """Start-up plane Poiseuille flow driven by body acceleration g (t = inf: steady)."""
+    y = np.asarray(y, dtype=float)
+    u = g * y * (H - y) / (2.0 * nu)
+    if not math.isinf(t):
+        for n in range(1, nterms + 1, 2):
+            u = u - 4.0 * g * H * H / (nu * n ** 3 * math.pi ** 3) * np.sin(n * math.pi * y / H) * \
+                math.exp(-n * n * math.pi * math.pi * nu * t / (H * H))
+    return u
+
+
+# ----------------------------------------------------------------------------
+# Cases
+# ----------------------------------------------------------------------------
+
+@dataclass
+class Case:
+    name: str
+    mesh: Mesh
+    Q: int
+    rho0: float
+    nu: float
+    dt: float
+    rho: np.ndarray
+    u: np.ndarray
+    steps: int
+    g: tuple = (0.0, 0.0, 0.0)
+    filter: Optional[str] = None
+    filter_kc: int = 2
+    filter_amp: float = 0.0
+    filter_order: float = 2.0
+    rk: str = "ssprk3"
+    meta: dict = field(default_factory=dict)
+
+    # convenience views
+    @property
+    def dim(self):
+        return self.mesh.dim
+
+    @property
+    def N(self):
+        return self.mesh.N
+
+    @property
+    def xyz(self):
+        return self.mesh.xyz
+
+    @property
+    def gid(self):
+        return self.mesh.gid
+
+    @property
+    def face_tag(self):
+        return self.mesh.face_tag
+
+    @property
+    def wall_u(self):
+        return self.mesh.wall_u
+
+    @property
+    def E(self):
+        return self.mesh.E
+
+    @property
+    def np_(self):
+        return self.mesh.np_
+
+    @property
+    def nv(self):
+        return self.E * self.np_ * self.Q
+
+
+def stable_dt(mesh: Mesh, cfl: float = 0.5) -> float:
+    """dt = cfl * h_min / max_a |e_a|_1, with |e_a|_1 = dim for the full lattices."""
+    return cfl * min_node_spacing(mesh) / mesh.dim
+
+
+FILTER_PAPER = dict(filter="quad", filter_kc=2, filter_amp=0.1, filter_order=2.0)
+FILTER_EXP = dict(filter="exp", filter_kc=None, filter_amp=36.0, filter_order=16.0)
+
+
+def _filter_kw(spec, N):
+    if spec is None or spec == "none":
+        return dict(filter=None)
+    if spec == "quad":
+        return dict(FILTER_PAPER)
+    if spec == "exp":
+        kw = dict(FILTER_EXP)
+        kw["filter_kc"] = (2 * N) // 3
+        return kw
+    raise ValueError(spec)
+
+
+def case_tgv2d(nel=8, N=5, Re=100.0, u0=0.05, steps=200, filt=None, cfl=0.5) -> Case:
+    """2D Taylor-Green vortex, D2Q9, periodic [0, 2 pi]^2."""
+    L = 2 * math.pi
+    mesh = box_mesh(2, N, (nel, nel), (0, 0), (L, L), (True, True))
+    nu = u0 * 1.0 / Re
+    dt = stable_dt(mesh, cfl)
+    rho, u = tgv2d_fields(mesh.xyz, u0)
+    return Case("tgv2d", mesh, 9, 1.0, nu, dt, rho, u, steps, meta=dict(u0=u0, Re=Re),
+                **_filter_kw(filt, N))
+
+
+def case_double_shear(nel=32, N=7, Re=1.0e4, Ma=0.1, kappa=80.0, delta=0.05, steps=2000,
+                      filt="exp", cfl=0.5) -> Case:
+    """Double shear layer, D2Q9, periodic unit square."""
+    mesh = box_mesh(2, N, (nel, nel), (0, 0), (1, 1), (True, True))
+    u0 = Ma * CS
+    nu = u0 * 1.0 / Re
+    dt = stable_dt(mesh, cfl)
+    rho, u = double_shear_fields(mesh.xyz, u0, kappa, delta)
+    return Case("double_shear", mesh, 9, 1.0, nu, dt, rho, u, steps,
+                meta=dict(u0=u0, Re=Re, kappa=kappa, delta=delta), **_filter_kw(filt, N))
+
+
+def channel_warp(seed=2509, amp=0.0125, Lx=2.0, H=1.0, kx=1, ky=1):
+    """Seeded sinusoidal displacement of channel nodes: zero on the walls,
+    periodic in x with period Lx / k."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ph = rng.uniform(0.0, 2 * math.pi, size=2)
+
+    def warp(xyz):
+        x = xyz[..., 0]
+        y = xyz[..., 1]
+        s = np.sin(math.pi * y / H)
+        out = xyz.copy()
+        out[..., 0] = x + amp * s * np.sin(2 * math.pi * kx * x / Lx + ph[0])
+        out[..., 1] = y + amp * s * np.sin(2 * math.pi * ky * x / Lx + ph[1])
+        return out
+
+    return warp
+
+
+def _channel_mesh(nelx, nely, N, Lx, H, curved, top_u, seed):
+    warp = channel_warp(seed=seed, amp=0.1 * (H / nely), Lx=Lx, H=H) if curved else None
+    return box_mesh(2, N, (nelx, nely), (0, 0), (Lx, H), (True, False),
+                    wall_tags={1: (1, 2)}, wall_u=[[0.0, 0.0], [top_u, 0.0]], warp=warp)
+
+
+def case_poiseuille(nelx=16, nely=8, N=7, Re=100.0, umax=0.1 / 3.0, Lx=2.0, H=1.0,
+                    curved=False, steps=200, seed=2509, cfl=0.5, filt=None) -> Case:
+    """Plane Poiseuille flow driven by a body acceleration g = 8 nu umax / H^2,
+    FBB walls at y = 0 and y = H, periodic in x, starting from rest."""
+    mesh = _channel_mesh(nelx, nely, N, Lx, H, curved, 0.0, seed)
+    nu = umax * H / Re
+    g = 8.0 * nu * umax / (H * H)
+    dt = stable_dt(mesh, cfl)
+    rho, u = rest_fields(mesh.xyz)
+    return Case("poiseuille" + ("_curved" if curved else ""), mesh, 9, 1.0, nu, dt, rho, u, steps,
+                g=(g, 0.0, 0.0), meta=dict(umax=umax, Re=Re, H=H, gx=g), **_filter_kw(filt, N))
+
+
+def case_couette(nelx=16, nely=8, N=7, Re=10.0, Ma=0.1, Lx=2.0, H=1.0, curved=False, steps=200,
+                 seed=2509, cfl=0.5, filt=None) -> Case:
+    """Start-up Couette flow: wall at y = 0 at rest, wall at y = H moving at U."""
+    U = Ma * CS
+    mesh = _channel_mesh(nelx, nely, N, Lx, H, curved, U, seed)
+    nu = U * H / Re
+    dt = stable_dt(mesh, cfl)
+    rho, u = rest_fields(mesh.xyz)
+    return Case("couette" + ("_curved" if curved else ""), mesh, 9, 1.0, nu, dt, rho, u, steps,
+                meta=dict(U=U, Re=Re, H=H), **_filter_kw(filt, N))
+
+
+def case_tgv3d(nel=16, N=7, Q=27, Re=1600.0, Ma=0.1, steps=5000, filt="quad", cfl=0.5) -> Case:
+    """3D Taylor-Green vortex, periodic [0, 2 pi]^3, L0 = 1."""
+    L = 2 * math.pi
+    mesh = box_mesh(3, N, (nel,) * 3, (0, 0, 0), (L, L, L), (True, True, True))
+    u0 = Ma * CS
+    nu = u0 * 1.0 / Re
+    dt = stable_dt(mesh, cfl)
+    rho, u = tgv3d_fields(mesh.xyz, u0)
+    return Case("tgv3d", mesh, Q, 1.0, nu, dt, rho, u, steps, meta=dict(u0=u0, Re=Re),
+                **_filter_kw(filt, N))
+
+
+def random_state(case: Case, seed: int = 7, amp: float = 0.01):
+    """Seeded perturbation of a case's initial fields, drawn per global node so
+    that every copy of a shared node gets the same value (continuous fields)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ng = int(case.gid.max()) + 1
+    dr = rng.standard_normal(ng)[case.gid]
+    du = rng.standard_normal((ng, case.dim))[case.gid]
+    return case.rho + amp * dr, case.u + amp * 0.1 * du

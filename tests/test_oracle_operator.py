@@ -1,0 +1,321 @@
+"""Pins of the oracle's spatial operator: geometry, exactness of the
+streaming operator, assembly, skew-symmetry, exact transport, the wall flux
+and conservation (Sec. 2.2, 2.2.1)."""
+import math
+
+import numpy as np
+import pytest
+
+from conftest import nerr
+from paper_2509_19171_amd import inputs as I
+
+
+def _sim(oracle_mod, mesh, Q, nu=0.01, dt=0.01, **kw):
+    return oracle_mod.OracleSim(mesh.dim, mesh.N, mesh.xyz, mesh.gid, mesh.face_tag, mesh.wall_u, Q,
+                                1.0, nu, dt, **kw)
+
+
+def _open_box(dim, N, nel, lo=None, hi=None, warp=None):
+    """Non-periodic box whose boundary faces carry tag 0 (no flux)."""
+    lo = lo or (0.0,) * dim
+    hi = hi or (1.0,) * dim
+    return I.box_mesh(dim, N, (nel,) * dim, lo, hi, (False,) * dim, wall_tags={m: (0, 0) for m in range(dim)},
+                      warp=warp)
+
+
+def _skew_warp(dim):
+    A = np.array([[1.0, 0.3, 0.1], [-0.2, 0.9, 0.2], [0.1, 0.05, 1.1]])[:dim, :dim]
+
+    def warp(x):
+        return x @ A.T + 0.1
+
+    return warp
+
+
+def _curved_warp(x):
+    out = x.copy()
+    out[..., 0] = x[..., 0] + 0.04 * np.sin(math.pi * x[..., 1]) * np.sin(2 * math.pi * x[..., 0])
+    out[..., 1] = x[..., 1] + 0.03 * np.sin(math.pi * x[..., 0]) * np.cos(math.pi * x[..., 1])
+    return out
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_geometry_affine(oracle_mod, dim):
+    mesh = _open_box(dim, 4, 2, warp=_skew_warp(dim))
+    s = _sim(oracle_mod, mesh, 9 if dim == 2 else 27)
+    wJ, G, J = s.geometry()
+    A = np.array([[1.0, 0.3, 0.1], [-0.2, 0.9, 0.2], [0.1, 0.05, 1.1]])[:dim, :dim]
+    h = 0.5  # element size before the affine map; reference size 2
+    Jexp = np.linalg.det(A) * (h / 2) ** dim
+    np.testing.assert_allclose(J, Jexp, rtol=1e-12)
+    # sum of wJ = volume of the mapped unit box
+    assert abs(wJ.sum() - abs(np.linalg.det(A))) < 1e-12
+    # G_mk = wJ dr_m/dx_k with dr/dx = (A h/2)^-1
+    Binv = np.linalg.inv(A * (h / 2))
+    np.testing.assert_allclose(G[..., :dim, :dim], wJ[..., None, None] * Binv, atol=1e-12)
+
+
+def _poly(x, deg):
+    """A polynomial of total degree deg in the physical coordinates (so of
+    degree <= deg in each reference coordinate on affine elements) and its
+    gradient: (a.x + b)^deg + (c.x + d)^(deg - 1) / 2."""
+    dim = x.shape[-1]
+    a = np.array([0.7, -0.4, 0.3])[:dim]
+    c = np.array([-0.2, 0.9, 0.5])[:dim]
+    p = x @ a + 0.3
+    q = x @ c - 0.1
+    f = p ** deg + 0.5 * q ** (deg - 1)
+    grad = deg * p[..., None] ** (deg - 1) * a + 0.5 * (deg - 1) * q[..., None] ** max(deg - 2, 0) * c
+    return f, grad
+
+
+@pytest.mark.parametrize("dim,Q,N", [(2, 9, 3), (2, 9, 6), (3, 27, 3), (3, 19, 4)])
+def test_streaming_operator_exact_on_polynomials(oracle_mod, dim, Q, N):
+    """-M^-1 C_a f = -e_a . grad f exactly for polynomials of degree <= N on
+    affine elements, at every node, after assembly."""
+    mesh = _open_box(dim, N, 2, warp=_skew_warp(dim))
+    s = _sim(oracle_mod, mesh, Q)
+    e, _, _ = oracle_mod.lattice(dim, Q)
+    fv, grad = _poly(mesh.xyz, N)
+    f = np.repeat(fv[:, None, :], Q, axis=1)
+    r = s.rhs(f)
+    exact = -np.einsum("ak,epk->eap", e, grad)
+    assert nerr(r, exact) < 1e-12
+    # the element-local contribution before assembly is -wJ e . grad f
+    wJ, _, _ = s.geometry()
+    np.testing.assert_allclose(s.rhs_local(f), wJ[:, None, :] * exact, atol=1e-12)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_linear_fields_exact_on_curved_mesh(oracle_mod, dim):
+    """Physical coordinates are in the isoparametric space, so gradients of
+    linear fields are exact on curved elements."""
+    if dim == 2:
+        warp = _curved_warp
+    else:
+        def warp(x):
+            out = x.copy()
+            out[..., 0] += 0.03 * np.sin(math.pi * x[..., 1]) * np.sin(math.pi * x[..., 2])
+            out[..., 2] += 0.02 * np.sin(math.pi * x[..., 0])
+            return out
+    Q = 9 if dim == 2 else 27
+    mesh = _open_box(dim, 5, 2, warp=warp)
+    s = _sim(oracle_mod, mesh, Q)
+    e, _, _ = oracle_mod.lattice(dim, Q)
+    c = np.array([0.3, -0.7, 0.5][:dim])
+    fv = mesh.xyz @ c + 0.2
+    f = np.repeat(fv[:, None, :], Q, axis=1)
+    r = s.rhs(f)
+    exact = -np.broadcast_to((e @ c)[None, :, None], r.shape)
+    assert nerr(r, exact) < 1e-11
+
+
+@pytest.mark.parametrize("dim,Q", [(2, 9), (3, 27)])
+def test_skew_symmetry_periodic_affine(oracle_mod, dim, Q):
+    """On periodic affine meshes sum_g M_g f_g (M^-1 (-C f))_g = 0: with
+    constant metric terms the collocation operator is skew in the mass inner
+    product (GLL summation by parts)."""
+    mesh = I.box_mesh(dim, 4, (3,) * dim, (0,) * dim, (1,) * dim, (True,) * dim)
+    s = _sim(oracle_mod, mesh, Q)
+    rng = np.random.Generator(np.random.PCG64(11))
+    ng = int(mesh.gid.max()) + 1
+    f = rng.standard_normal((ng, Q))[mesh.gid].transpose(0, 2, 1).copy()
+    r = s.rhs(f)
+    M = s.mass()
+    # sum over local nodes of (wJ f r) counts each global node's M_g f r once
+    wJ, _, _ = s.geometry()
+    val = np.einsum("ep,eap,eap->", wJ, f, r)
+    scale = np.einsum("ep,eap,eap->", wJ, np.abs(f), np.abs(r))
+    assert abs(val) < 1e-13 * scale
+    # copies of a shared node receive the same assembled value
+    flat = r.transpose(0, 2, 1).reshape(-1, Q)
+    gid = mesh.gid.reshape(-1)
+    order = np.argsort(gid, kind="stable")
+    gs = gid[order]
+    same = gs[1:] == gs[:-1]
+    assert np.abs(flat[order][1:][same] - flat[order][:-1][same]).max() < 1e-13
+    assert np.all(M > 0)
+
+
+def test_discrete_conservation_curved_2d(oracle_mod):
+    """On curved 2D periodic meshes the element contributions sum to zero for
+    any continuous f: the discrete metric identity holds for isoparametric
+    maps, so the streaming operator conserves mass exactly (it is not skew
+    there: the collocation product is not summation-by-parts with variable
+    metric terms)."""
+    mesh = I.box_mesh(2, 6, (3, 3), (0, 0), (1, 1), (True, True), warp=_periodic_curved_warp)
+    s = _sim(oracle_mod, mesh, 9)
+    rng = np.random.Generator(np.random.PCG64(12))
+    ng = int(mesh.gid.max()) + 1
+    f = rng.standard_normal((ng, 9))[mesh.gid].transpose(0, 2, 1).copy()
+    rt = s.rhs_local(f)
+    tot = rt.sum(axis=(0, 2))
+    assert np.abs(tot).max() < 1e-13 * np.abs(rt).sum()
+
+
+def _periodic_curved_warp(x):
+    out = x.copy()
+    out[..., 0] = x[..., 0] + 0.03 * np.sin(2 * math.pi * x[..., 1]) * np.sin(2 * math.pi * x[..., 0])
+    out[..., 1] = x[..., 1] + 0.03 * np.sin(2 * math.pi * x[..., 0]) * np.cos(2 * math.pi * x[..., 1])
+    return out
+
+
+def test_exact_transport_spectral_convergence(oracle_mod):
+    """Streaming alone (no collision, no force) on a periodic box transports
+    f_a(x, 0) to f_a(x - e_a t); the error falls spectrally with N until the
+    third-order time error takes over."""
+    errs = []
+    for N in (3, 5, 7):
+        mesh = I.box_mesh(2, N, (4, 4), (0, 0), (2 * math.pi, 2 * math.pi), (True, True))
+        dt = 0.25 * I.min_node_spacing(mesh) / 2
+        s = _sim(oracle_mod, mesh, 9, dt=dt)
+        e, _, _ = oracle_mod.lattice(2, 9)
+        x = mesh.xyz
+
+        def field(t):
+            return np.stack([np.sin(x[..., 0] - e[a, 0] * t) * np.cos(x[..., 1] - e[a, 1] * t) + 0.3 *
+                             np.cos(2 * (x[..., 0] - e[a, 0] * t)) for a in range(9)], axis=1)
+
+        s.set_f(field(0.0))
+        nsteps = int(round(0.5 / dt))
+        s.advect(nsteps)
+        errs.append(nerr(s.get_f(), field(s.time)))
+    assert errs[0] > 3 * errs[1] > 9 * errs[2]
+    assert errs[2] < 2e-5
+
+
+def test_transport_third_order_in_time(oracle_mod):
+    mesh = I.box_mesh(2, 10, (2, 2), (0, 0), (2 * math.pi, 2 * math.pi), (True, True))
+    e, _, _ = oracle_mod.lattice(2, 9)
+    x = mesh.xyz
+    T = 0.6
+    errs = []
+    for nst in (40, 80):
+        dt = T / nst
+        s = _sim(oracle_mod, mesh, 9, dt=dt)
+
+        def field(t):
+            return np.stack([np.sin(x[..., 0] - e[a, 0] * t + x[..., 1] - e[a, 1] * t) for a in range(9)], axis=1)
+
+        s.set_f(field(0.0))
+        s.advect(nst)
+        errs.append(nerr(s.get_f(), field(T)))
+    rate = math.log2(errs[0] / errs[1])
+    assert 2.7 < rate < 3.4, (errs, rate)
+
+
+@pytest.mark.parametrize("curved", [False, True])
+def test_wall_rest_state_steady_and_mass(oracle_mod, curved):
+    """Rest equilibrium between FBB walls stays at rest to round-off; a
+    disturbed state conserves total mass to round-off (the incoming-only flux
+    cancels the boundary term of the streaming operator)."""
+    c = I.case_couette(nelx=3, nely=2, N=5, curved=curved)
+    mesh = c.mesh
+    mesh.wall_u[:] = 0.0
+    s = _sim(oracle_mod, mesh, 9, nu=c.nu, dt=c.dt)
+    rho, u = I.rest_fields(mesh.xyz)
+    s.init(rho, u)
+    f0 = s.get_f()
+    s.step(20)
+    assert np.abs(s.get_f() - f0).max() < 1e-14
+    # disturbed
+    s2 = _sim(oracle_mod, mesh, 9, nu=c.nu, dt=c.dt)
+    rng = np.random.Generator(np.random.PCG64(3))
+    ng = int(mesh.gid.max()) + 1
+    s2.init(rho + 0.01 * rng.standard_normal(ng)[mesh.gid],
+            0.01 * rng.standard_normal((ng, 2))[mesh.gid])
+    m0 = s2.reduce()[0]
+    s2.step(30)
+    assert abs(s2.reduce()[0] - m0) < 1e-13 * m0
+
+
+def test_moving_wall_flux_mass_neutral(oracle_mod):
+    """The moving-wall term of the bounce-back jump adds no mass for
+    tangential wall motion."""
+    c = I.case_couette(nelx=3, nely=2, N=5)
+    s = oracle_mod.from_case(c)
+    m0 = s.reduce()[0]
+    s.step(30)
+    assert abs(s.reduce()[0] - m0) < 1e-13 * m0
+    # and the wall drags the fluid in its own direction
+    _, u = s.moments()
+    top = c.xyz[..., 1] > 0.9
+    assert u[..., 0][top].mean() > 0
+
+
+def test_wall_flux_incoming_only(oracle_mod):
+    """At a wall node the flux changes only directions with n.e < 0; on the
+    bottom wall (n = -y) these are the directions with e_y > 0."""
+    c = I.case_couette(nelx=2, nely=2, N=3)
+    c.mesh.wall_u[:] = 0
+    s = _sim(oracle_mod, c.mesh, 9, nu=c.nu, dt=c.dt)
+    nowall = c.mesh.face_tag.copy()
+    nowall[:] = 0
+    s_nw = oracle_mod.OracleSim(2, c.N, c.xyz, c.gid, nowall, None, 9, 1.0, c.nu, c.dt)
+    rng = np.random.Generator(np.random.PCG64(9))
+    f = 0.1 + 0.01 * rng.standard_normal((c.E, 9, c.np_))
+    diff = s.rhs_local(f) - s_nw.rhs_local(f)
+    e, t, opp = oracle_mod.lattice(2, 9)
+    bottom = (c.xyz[..., 1] < 1e-12)
+    for a in range(9):
+        d = diff[:, a, :]
+        if e[a, 1] > 0:
+            assert np.abs(d[bottom]).max() > 0
+        else:
+            assert np.abs(d[bottom]).max() == 0
+    # the incoming-direction flux equals (w_s J_s n.e_a)(f_a - f_b) with
+    # w_s J_s = GLL weight x half the element width on this flat wall
+    xi, w = oracle_mod.gll(c.N)
+    el = 0  # bottom-left element
+    hx = 2.0 / 2 / 2  # element width / 2 (nelx = 2 over Lx = 2)
+    for a in range(9):
+        if e[a, 1] <= 0:
+            continue
+        for i in range(c.N + 1):
+            p = i
+            exp = w[i] * hx * (-e[a, 1]) * (f[el, a, p] - f[el, opp[a], p])
+            assert abs(diff[el, a, p] - exp) < 1e-15
+
+
+@pytest.mark.parametrize("dim,Q", [(2, 9), (3, 27)])
+def test_periodic_conservation_with_filter(oracle_mod, dim, Q):
+    """Mass and momentum are conserved to round-off on periodic affine meshes
+    (collision, streaming and the k_c >= 2 filter all conserve them); with a
+    body acceleration the momentum grows by dt g (total mass) per step."""
+    mesh = I.box_mesh(dim, 4, (3,) * dim, (0,) * dim, (1,) * dim, (True,) * dim,
+                      warp=None)
+    rng = np.random.Generator(np.random.PCG64(21))
+    ng = int(mesh.gid.max()) + 1
+    rho = 1 + 0.01 * rng.standard_normal(ng)[mesh.gid]
+    u = 0.02 * rng.standard_normal((ng, dim))[mesh.gid]
+    dt = 0.5 * I.min_node_spacing(mesh) / dim
+    s = _sim(oracle_mod, mesh, Q, nu=0.01, dt=dt, filter="quad", filter_kc=2, filter_amp=0.1)
+    s.init(rho, u)
+    r0 = s.reduce()
+    s.step(10)
+    r1 = s.reduce()
+    assert abs(r1[0] - r0[0]) < 1e-13 * r0[0]
+    assert np.abs(r1[1:1 + dim] - r0[1:1 + dim]).max() < 1e-14
+    g = np.array([1e-3, 2e-3, -1e-3][:dim])
+    s = _sim(oracle_mod, mesh, Q, nu=0.01, dt=dt, g=tuple(g), filter="quad", filter_kc=2, filter_amp=0.1)
+    s.init(rho, u)
+    r0 = s.reduce()
+    s.step(5)
+    r1 = s.reduce()
+    np.testing.assert_allclose(r1[1:1 + dim] - r0[1:1 + dim], 5 * dt * g * r0[0], rtol=1e-10, atol=1e-16)
+
+
+def test_filter_step_preserves_continuity_and_mass(oracle_mod):
+    mesh = I.box_mesh(2, 6, (3, 3), (0, 0), (1, 1), (True, True), warp=_periodic_curved_warp)
+    rng = np.random.Generator(np.random.PCG64(5))
+    ng = int(mesh.gid.max()) + 1
+    f = (0.1 + 0.01 * rng.standard_normal((ng, 9)))[mesh.gid].transpose(0, 2, 1).copy()
+    s = _sim(oracle_mod, mesh, 9, filter="exp", filter_kc=4, filter_amp=36.0, filter_order=16.0)
+    ff = s.filter(f)
+    flat = ff.transpose(0, 2, 1).reshape(-1, 9)
+    gid = mesh.gid.reshape(-1)
+    order = np.argsort(gid, kind="stable")
+    gs = gid[order]
+    same = gs[1:] == gs[:-1]
+    assert np.abs(flat[order][1:][same] - flat[order][:-1][same]).max() < 1e-15
+    assert np.abs(ff - f).max() > 1e-6
