@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Throughput of the filtered SELBM time step on one MI355X.
+
+Workload: the 3D Taylor-Green vortex, D3Q27, periodic [0, 2 pi]^3 split into
+16^3 hexahedra of order N = 7 (4096 elements, 512 nodes each, 56.6 M
+node-velocities), Re = 1600, Ma = 0.1, the paper's quadratic filter
+(gamma = 0.1, k_c = 2), SSPRK3, inputs resident in HBM. The headline form is
+FP32 deviation storage; the FP64 form is timed beside it.
+
+Prints ONE JSON line. ``value`` is node-velocity updates per second (1e9,
+local nodes E (N+1)^3 Q per step). ``roofline`` refers to the dominant kernel
+(its average duration measured here with HIP events); ``step`` gives the same
+for the whole step against the method's algorithmic bytes; ``cpu_baseline``
+times the FP64 CPU oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "node-velocity updates/sec (GLUPS) and % HBM roofline, FP64 vs FP32 vs closure"
+PEAK_HBM_GBS = 8000.0
+COUNTERS = os.path.join(ROOT, "profiles", "k_stage23_tgv3d_n7_q27_fp32dev_counters.json")
+
+
+def src_hash() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2509_19171_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        with open(os.path.join(d, name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(info, Q, s):
+    """Bytes per launch and per step from the method's minimum traffic.
+
+    Per step (all kernels): 8 state accesses per local node-velocity (SSPRK3:
+    read f, write f1; read f, f1, write f2; read f, f2, write f) plus the
+    metric and mass weight (dim^2 + 1 values per node) once per stage.
+    Later-stage element kernel (one launch): reads every unique operand value
+    once, reads the post-collision state and writes the result at element
+    interior nodes, writes the element contributions of element-boundary
+    nodes, and reads the metric, interior inverse mass and density."""
+    E, npn, dim = info["E"], info["np"], info["dim"]
+    nb = info["boundary_nodes_per_element"]
+    ni = npn - nb
+    G = info["unique_nodes"]
+    nv = E * npn * Q
+    step = s * nv * (8 + 3 * (dim * dim + 1) / Q)
+    stage23 = s * (Q * G + 2 * Q * E * ni + Q * E * nb + E * npn * dim * dim + 2 * E * ni)
+    return nv, step, stage23
+
+
+def time_form(case, precision, steps, warmup, torch):
+    from paper_2509_19171_amd import sel
+
+    sim = sel.from_case(case, precision)
+    info = sim.mesh.info()
+    sim.step(warmup)
+    sim.sync()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    sim.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    # second timed window: HIP events around every launch for per-kernel durations
+    kern = sim.step_timed(steps)
+    sim.sync()
+    out = dict(ms_total=ms, ms_per_step=ms / steps, kernels=kern, info=info)
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(case, budget_s=15.0):
+    import oracle
+
+    o = oracle.from_case(case)
+    t0 = time.perf_counter()
+    o.step(1)
+    t1 = time.perf_counter() - t0
+    n = 1
+    extra = int(max(0, min(8, budget_s / max(t1, 1e-3) - 1)))
+    if extra:
+        t0 = time.perf_counter()
+        o.step(extra)
+        t1 += time.perf_counter() - t0
+        n += extra
+    nv = case.nv
+    return {"value": nv * n / t1 / 1e9, "unit": "GNVU/s", "cores": oracle.get_threads(), "kind": "oracle",
+            "sample": f"{n} FP64 step(s) of the same 16^3 N=7 D3Q27 workload (whole mesh, {t1:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", default="fp32dev", choices=["fp32dev", "fp64"])
+    ap.add_argument("--nel", type=int, default=16)
+    ap.add_argument("--order", type=int, default=7)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-other-form", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU decomposition is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2509_19171_amd import inputs as I
+    from paper_2509_19171_amd import sel
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    sel.load()
+    case = I.case_tgv3d(nel=args.nel, N=args.order, steps=0)
+    forms = {}
+    order = [args.precision] + ([] if args.no_other_form else [p for p in ("fp32dev", "fp64") if p != args.precision])
+    for prec in order:
+        k = args.steps if prec == args.precision else max(20, args.steps // 2)
+        w = args.warmup if prec == args.precision else max(5, args.warmup // 2)
+        print(f"[bench] timing {prec}: {w} warmup + {k} steps", file=sys.stderr, flush=True)
+        forms[prec] = time_form(case, prec, k, w, torch)
+
+    head = forms[args.precision]
+    info = head["info"]
+    s = 4 if args.precision == "fp32dev" else 8
+    nv, step_bytes, stage23_bytes = algorithmic_bytes(info, case.Q, s)
+    value = nv / (head["ms_per_step"] * 1e-3) / 1e9
+    kern = head["kernels"]
+    dom = max(kern, key=lambda k: kern[k][0])
+    dom_ms = kern[dom][0] / max(kern[dom][1], 1)
+    per_launch = {"stage23": stage23_bytes}.get(dom)
+    roof = None
+    if per_launch is not None:
+        ach = per_launch / (dom_ms * 1e-3) / 1e9
+        traffic = None
+        if os.path.exists(COUNTERS):
+            with open(COUNTERS) as fh:
+                cnt = json.load(fh)
+            if cnt.get("src_hash") == src_hash() and cnt.get("precision") == args.precision:
+                traffic = cnt.get("hbm_bytes_per_launch")
+        roof = {"bound": "hbm", "kernel": "k_stage (later SSPRK stages)", "achieved": round(ach, 1),
+                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4),
+                "traffic": traffic, "algorithmic_bytes_per_launch": int(per_launch),
+                "avg_launch_ms": round(dom_ms, 5)}
+    step_gbs = step_bytes / (head["ms_per_step"] * 1e-3) / 1e9
+    result = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "GNVU/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32dev" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"3D Taylor-Green vortex, D3Q27, periodic [0,2pi]^3, {args.nel}^3 hexes, "
+                               f"N={args.order}, Re=1600, Ma=0.1, quadratic filter, SSPRK3",
+                   "precision": args.precision, "elements": info["E"], "order": args.order, "Q": case.Q,
+                   "local_nodes": info["E"] * info["np"], "unique_nodes": info["unique_nodes"],
+                   "node_velocities": nv},
+        "roofline": roof,
+        "step": {"algorithmic_bytes_per_step": int(step_bytes), "achieved": round(step_gbs, 1),
+                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(step_gbs / PEAK_HBM_GBS, 4)},
+        "kernels": {k: {"ms_total": round(v[0], 4), "launches": v[1],
+                        "avg_ms": round(v[0] / v[1], 5) if v[1] else None} for k, v in kern.items()},
+        "forms": {p: {"value": round(nv / (f["ms_per_step"] * 1e-3) / 1e9, 3),
+                      "ms_per_step": round(f["ms_per_step"], 5)} for p, f in forms.items()},
+        "src_hash": src_hash(),
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(case)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

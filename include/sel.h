@@ -1,0 +1,187 @@
+/*
+ * sel.h -- C interface of the MI355X (gfx950) filtered spectral-element
+ * lattice Boltzmann (SELBM) library with flux bounce-back walls
+ * (Zhao, Patel, Lin, Min & Lee, arXiv:2509.19171).
+ *
+ * One call of sel_step advances the discrete Boltzmann equation (Sec. 2.1,
+ * Eq. dbe_m) by whole time steps in the order of the scheme summary at the
+ * end of Sec. 2.2: BGK collision with the higher-order force F** (Sec. 2.1),
+ * streaming as a Galerkin spectral-element advection solved by SSP
+ * Runge-Kutta with the leading-order force F* and the flux bounce-back wall
+ * flux (Sec. 2.2, 2.2.1, 2.2.2), then the explicit modal filter (Sec. 2.2.3).
+ *
+ * Conventions (all arrays row-major, host memory unless stated):
+ *   dim 2 or 3; order N; np = (N+1)^dim nodes per element; node index
+ *   p = i + (N+1) j + (N+1)^2 k with the first reference direction r fastest
+ *   (Sec. 2.2, lumped mass index).
+ *   xyz  [E][np][dim]  GLL node coordinates of the isoparametric map.
+ *   gid  [E][np]       global node id in [0, E*np); every copy of a node shared
+ *                      by several elements (periodic copies included) has the
+ *                      same id. Only nodes on element faces may be shared.
+ *   face_tag [E][2*dim] faces ordered (r-, r+, s-, s+, t-, t+): 0 = interior or
+ *                      periodic, k >= 1 = wall k with velocity wall_u[k-1].
+ *   wall_u [ntags][dim] wall velocities u_b of the bounce-back jump.
+ *   rho [E][np], u [E][np][dim], f [E][Q][np]: FP64, full distribution f
+ *                      (the FP32 deviation form converts inside).
+ *   Velocities: a = a0 + 3 a1 (+ 9 a2) with component values {0, +1, -1}[a_i];
+ *   D2Q9 (dim 2), D3Q27 and D3Q19 (the D3Q27 entries with |e|^2 <= 2, same
+ *   order). Lattice units: particle speed 1, c_s^2 = 1/3.
+ *
+ * Errors: every call returns SEL_OK (0) or a negative SEL_E* code and never
+ * aborts; out-parameters are written only on success; sel_last_error() gives
+ * a thread-local message for the last failing call of the thread.
+ * Device work is enqueued on the caller's HIP stream; device faults and
+ * non-finite states surface at the next synchronising call.
+ */
+#ifndef SEL_H
+#define SEL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SEL_OK 0
+#define SEL_EINVAL (-1)      /* invalid argument, mesh or parameter */
+#define SEL_ENOMEM (-2)      /* host or device allocation failed, workspace too small */
+#define SEL_EDEVICE (-3)     /* HIP runtime or kernel launch error */
+#define SEL_ENONFINITE (-4)  /* the state holds NaN or Inf */
+#define SEL_ESTATE (-5)      /* call not valid in the current state */
+#define SEL_EUNSUPPORTED (-6) /* valid but not built (order, lattice, form) */
+
+/* storage and arithmetic of the distribution */
+#define SEL_FP64 0      /* f in FP64 */
+#define SEL_FP32_DEV 1  /* g = f - t_a rho0 stored and streamed in FP32; geometry set up in FP64 */
+
+/* filter transfer functions (Sec. 2.2.3) */
+#define SEL_FILTER_NONE 0
+#define SEL_FILTER_QUAD 1 /* sigma_k = 1 - amp ((k - kc)/(N - kc))^2, k > kc */
+#define SEL_FILTER_EXP 2  /* sigma_k = exp(-amp ((k - kc)/(N - kc))^order), k > kc */
+
+/* time marching (Sec. 2.2.2) */
+#define SEL_RK_SSP3 0     /* Shu-Osher SSPRK3 */
+#define SEL_RK_PRINTED4 1 /* the four printed stage formulas, L applied linearly */
+
+typedef struct sel_mesh sel_mesh;
+typedef struct sel_sim sel_sim;
+
+/* Physical and numerical parameters.
+ *   nu = lambda c_s^2 and tau = lambda / dt (Sec. 2.1); dt is stored as given.
+ *   accel: body acceleration g, force density F = rho g (Sec. 2.1, Eqs. body
+ *   and f_c; Sec. 3.5 drives the pipe with (0, 0, rho g)).
+ *   closure / closure_len: host pointer to the FP32 parameter blob of the
+ *   learned relaxation-time closure (layout in sel_closure_layout) or NULL. */
+typedef struct sel_params {
+    int32_t Q;           /* 9 (dim 2), 19 or 27 (dim 3) */
+    int32_t precision;   /* SEL_FP64 or SEL_FP32_DEV */
+    int32_t rk;          /* SEL_RK_* */
+    int32_t filter_type; /* SEL_FILTER_* */
+    int32_t filter_kc;   /* cut-off mode k_c, 0 <= kc < N */
+    int32_t reserved0;
+    double filter_amp;   /* gamma (quadratic) or alpha (exponential) */
+    double filter_order; /* exponent of the exponential filter */
+    double rho0;         /* reference density of the wall term and the deviation form */
+    double nu;           /* kinematic viscosity > 0 */
+    double dt;           /* time step > 0 */
+    double accel[3];     /* body acceleration g (entries beyond dim ignored) */
+    const float *closure;
+    int64_t closure_len;
+} sel_params;
+
+/* Mesh ingest. Copies every array (the caller keeps ownership) and checks:
+ * dim in {2,3}; supported N; E >= 1; gid in [0, E*np); nodes off the element
+ * faces are not shared; face_tag in [0, ntags]; wall_u given when ntags > 0.
+ * Element geometry (Jacobian > 0) is checked by sel_init on the device.
+ * Returns SEL_EINVAL, SEL_EUNSUPPORTED or SEL_ENOMEM on failure. */
+int sel_mesh_create(int32_t dim, int32_t N, int64_t E, const double *xyz, const int64_t *gid,
+                    const int32_t *face_tag, int32_t ntags, const double *wall_u, sel_mesh **out);
+int sel_mesh_destroy(sel_mesh *mesh);
+
+/* info[0..7] = dim, N, E, np, unique nodes, shared-node groups on element
+ * boundaries, element-boundary nodes per element, wall faces. */
+int sel_mesh_info(const sel_mesh *mesh, int64_t *info);
+
+/* Bytes of device workspace sel_init needs for this mesh and parameters. */
+int sel_workspace_bytes(const sel_mesh *mesh, const sel_params *p, size_t *bytes);
+
+/* Create a simulation and set f-bar = f^eq(rho, u) - dt F** / 2 (Sec. 2.1
+ * with f = f^eq). rho [E][np] and u [E][np][dim] are FP64 host arrays (shared
+ * copies must carry equal values). dev_ws is device memory of at least
+ * sel_workspace_bytes bytes owned by the caller, who keeps it alive until
+ * sel_destroy; NULL makes the library allocate it. hip_stream is a
+ * hipStream_t (NULL = default stream). The mesh may be destroyed after this
+ * call. Errors: SEL_EINVAL (bad parameter or non-positive Jacobian),
+ * SEL_ENOMEM, SEL_EDEVICE, SEL_EUNSUPPORTED. */
+int sel_init(const sel_mesh *mesh, const sel_params *p, const double *rho, const double *u,
+             void *dev_ws, size_t ws_bytes, void *hip_stream, sel_sim **out);
+
+/* Enqueue nsteps >= 0 time steps (asynchronous). */
+int sel_step(sel_sim *sim, int64_t nsteps);
+
+/* Same as sel_step, with HIP events recorded on the stream around every
+ * kernel launch. On return (it synchronises) ms[k] holds the summed device
+ * time and launches[k] the number of launches of kernel kind k:
+ *   0 first-stage element kernel (filter of the previous step, collision,
+ *     streaming operator), 1 later-stage element kernel (streaming operator),
+ *   2 shared-node assembly, 3 end-of-call filter. */
+#define SEL_NKIND 4
+int sel_step_timed(sel_sim *sim, int64_t nsteps, double *ms, int64_t *launches);
+
+/* Synchronise the stream; SEL_ENONFINITE if the state holds NaN or Inf. */
+int sel_sync(sel_sim *sim);
+
+/* Density and velocity of the current f-bar (Eqs. pressure, momentum):
+ * rho [E][np], u [E][np][dim], FP64 host arrays. Synchronises. */
+int sel_moments(sel_sim *sim, double *rho, double *u);
+
+/* Same on device: d_rho [E][np], d_u [E][np][dim] FP64 device arrays,
+ * enqueued on the stream, no synchronisation. */
+int sel_moments_device(sel_sim *sim, double *d_rho, double *d_u);
+
+/* FP64 integrals with the lumped mass: out[0] = sum wJ rho,
+ * out[1..dim] = sum wJ rho u, out[dim+1] = sum wJ rho0 |u|^2 / 2 (kinetic
+ * energy as in Sec. 3.4), out[dim+2] = number of non-finite f entries.
+ * Synchronises. */
+int sel_reduce(sel_sim *sim, double *out);
+
+/* Checkpoint access: f [E][Q][np] FP64 full distribution (host). set_f takes
+ * the value of the lowest-numbered copy of each shared node. Synchronise. */
+int sel_get_f(sel_sim *sim, double *f);
+int sel_set_f(sel_sim *sim, const double *f);
+
+/* Simulated time and step count. */
+int sel_get_time(const sel_sim *sim, double *t, int64_t *nstep);
+
+/* Operator pieces on a host state f [E][Q][np] (FP64 in and out), for
+ * checking the kernels one by one. Synchronises.
+ *   SEL_OP_RHS:       M^-1 (R(n.j) - C_a f) after assembly (Sec. 2.2, 2.2.1), no F*
+ *   SEL_OP_RHS_LOCAL: element contributions R(n.j) - C_a f before assembly
+ *   SEL_OP_COLLIDE:   post-collision f* (Sec. 2.1)
+ *   SEL_OP_FILTER:    filtered f (Sec. 2.2.3) */
+#define SEL_OP_RHS 0
+#define SEL_OP_RHS_LOCAL 1
+#define SEL_OP_COLLIDE 2
+#define SEL_OP_FILTER 3
+int sel_apply(sel_sim *sim, int32_t op, const double *fin, double *fout);
+
+/* Geometry computed on the device: wJ [E][np], J [E][np] (FP64 host). */
+int sel_geometry(sel_sim *sim, double *wJ, double *J);
+
+/* The hipStream_t the simulation enqueues its work on. */
+void *sel_stream(const sel_sim *sim);
+
+int sel_destroy(sel_sim *sim);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char *sel_last_error(void);
+
+/* Library build string (target, compiled orders). */
+const char *sel_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEL_H */

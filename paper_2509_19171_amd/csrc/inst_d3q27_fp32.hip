@@ -1,0 +1,20 @@
+// Explicit instantiation of the SELBM kernels: dim 3, Q 27, storage float.
+#include "launch_impl.h"
+
+namespace sel {
+
+const Ops *ops_d3q27_fp32(int N)
+{
+    switch (N) {
+    case 2: return Impl<3, 2, 27, float, true>::ops();
+    case 3: return Impl<3, 3, 27, float, true>::ops();
+    case 4: return Impl<3, 4, 27, float, true>::ops();
+    case 5: return Impl<3, 5, 27, float, true>::ops();
+    case 6: return Impl<3, 6, 27, float, true>::ops();
+    case 7: return Impl<3, 7, 27, float, true>::ops();
+    case 8: return Impl<3, 8, 27, float, true>::ops();
+    default: return nullptr;
+    }
+}
+
+}  // namespace sel

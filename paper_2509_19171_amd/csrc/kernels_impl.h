@@ -1,0 +1,641 @@
+// HIP kernels of the SELBM time step for gfx950, templated on the dimension,
+// the order N, the lattice Q, the storage type T and the deviation form DEV.
+//
+// Data layout (all device, one workspace):
+//   state arrays [Q][Gtot]: velocity-major; for each velocity the element
+//     interiors come first (element e, interior slot s at e*NI + s), then the
+//     shared element-boundary nodes, one entry per node group (Gi + g).
+//   element contributions of boundary nodes rtb [Q][E*NB] (element-major).
+//   metric Gm [E][DIM*DIM][NP] = wJ dr_m/dx_k, interior 1/wJ [E][NI],
+//   assembled inverse mass of boundary groups [ngrp].
+// One workgroup handles EPB elements with one thread per node; a velocity
+// plane of each element is staged in LDS for the tensor-product derivatives.
+#pragma once
+
+#include <type_traits>
+
+#include "sel_internal.h"
+
+namespace sel {
+
+constexpr double kCs2 = 1.0 / 3.0;
+
+__host__ __device__ constexpr int ipow_c(int b, int e) { return e == 0 ? 1 : b * ipow_c(b, e - 1); }
+
+// ---------------------------------------------------------------- lattice --
+// a = a0 + 3 a1 (+ 9 a2), component values {0, +1, -1}; D3Q19 keeps |e|^2 <= 2.
+template <int DIM, int Q>
+__host__ __device__ constexpr int lat_full(int a)
+{
+    if (Q != 19) return a;
+    int cnt = 0;
+    for (int f = 0; f < 27; ++f) {
+        int s = (f % 3 != 0) + ((f / 3) % 3 != 0) + (f / 9 != 0);
+        if (s > 2) continue;
+        if (cnt == a) return f;
+        ++cnt;
+    }
+    return 0;
+}
+template <int DIM, int Q>
+__host__ __device__ constexpr int lat_e(int a, int k)
+{
+    if (k >= DIM) return 0;
+    int f = lat_full<DIM, Q>(a);
+    int c = (k == 0) ? f % 3 : (k == 1) ? (f / 3) % 3 : f / 9;
+    return c == 0 ? 0 : (c == 1 ? 1 : -1);
+}
+template <int DIM, int Q>
+__host__ __device__ constexpr int lat_s2(int a)
+{
+    return lat_e<DIM, Q>(a, 0) * lat_e<DIM, Q>(a, 0) + lat_e<DIM, Q>(a, 1) * lat_e<DIM, Q>(a, 1) +
+           lat_e<DIM, Q>(a, 2) * lat_e<DIM, Q>(a, 2);
+}
+template <int DIM, int Q>
+__host__ __device__ constexpr double lat_t(int a)
+{
+    int s = lat_s2<DIM, Q>(a);
+    if (Q == 9) return s == 0 ? 4.0 / 9.0 : s == 1 ? 1.0 / 9.0 : 1.0 / 36.0;
+    if (Q == 19) return s == 0 ? 1.0 / 3.0 : s == 1 ? 1.0 / 18.0 : 1.0 / 36.0;
+    return s == 0 ? 8.0 / 27.0 : s == 1 ? 2.0 / 27.0 : s == 2 ? 1.0 / 54.0 : 1.0 / 216.0;
+}
+template <int DIM, int Q>
+__host__ __device__ constexpr int lat_opp(int a)
+{
+    for (int b = 0; b < Q; ++b)
+        if (lat_e<DIM, Q>(b, 0) == -lat_e<DIM, Q>(a, 0) && lat_e<DIM, Q>(b, 1) == -lat_e<DIM, Q>(a, 1) &&
+            lat_e<DIM, Q>(b, 2) == -lat_e<DIM, Q>(a, 2))
+            return b;
+    return 0;
+}
+
+template <int I, int END, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (I < END) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, END>(f);
+    }
+}
+
+template <int DIM, int N>
+struct Geo {
+    static constexpr int n1 = N + 1;
+    static constexpr int NP = ipow_c(n1, DIM);
+    static constexpr int NI = ipow_c(N - 1, DIM);
+    static constexpr int NB = NP - NI;
+    static constexpr int EPB = (NP >= 256) ? 1 : 256 / NP;
+    static constexpr int BLOCK = EPB * NP;
+};
+
+// Workgroups are dispatched round-robin over the 8 XCDs; hand each XCD a
+// contiguous range of element blocks so that neighbours share its L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t nblk)
+{
+    const int64_t x = blockIdx.x;
+    const int64_t per = (nblk + 7) / 8;
+    return (x % 8) * per + x / 8;
+}
+inline int64_t xcd_grid(int64_t nblk) { return 8 * ((nblk + 7) / 8); }
+
+// --------------------------------------------------------- local physics --
+// BGK collision with the higher-order force F** (Sec. 2.1): from the node's
+// values v[a] (full f, or the deviation g = f - t_a rho0 when DEV) compute
+// rho, u = sum e f / rho, F = rho g and
+//   f* = f - omega (f - (f^eq - dt F**/2)) + dt F**,  omega = 1 / (tau + 1/2).
+template <int DIM, int Q, typename T, bool DEV>
+__device__ __forceinline__ void collide_node(T (&v)[Q], T rho0, T omega, T dt, const T (&g)[3], T &rho_out)
+{
+    T m0 = 0, j0 = 0, j1 = 0, j2 = 0;
+    static_for<0, Q>([&](auto A) {
+        constexpr int a = decltype(A)::value;
+        m0 += v[a];
+        if constexpr (lat_e<DIM, Q>(a, 0) != 0) j0 += T(lat_e<DIM, Q>(a, 0)) * v[a];
+        if constexpr (lat_e<DIM, Q>(a, 1) != 0) j1 += T(lat_e<DIM, Q>(a, 1)) * v[a];
+        if constexpr (lat_e<DIM, Q>(a, 2) != 0) j2 += T(lat_e<DIM, Q>(a, 2)) * v[a];
+    });
+    const T rho = DEV ? rho0 + m0 : m0;
+    const T inv = T(1) / rho;
+    const T u0 = j0 * inv, u1 = j1 * inv, u2 = j2 * inv;
+    const T F0 = rho * g[0], F1 = rho * g[1], F2 = rho * g[2];
+    const T uu = u0 * u0 + u1 * u1 + u2 * u2;
+    const T uF = u0 * F0 + u1 * F1 + u2 * F2;
+    const T c1 = T(3), c2 = T(4.5), c3 = T(1.5);  // 1/cs2, 1/(2 cs4), 1/(2 cs2)
+    const T half_dt = T(0.5) * dt;
+    static_for<0, Q>([&](auto A) {
+        constexpr int a = decltype(A)::value;
+        constexpr int ex = lat_e<DIM, Q>(a, 0), ey = lat_e<DIM, Q>(a, 1), ez = lat_e<DIM, Q>(a, 2);
+        const T t = T(lat_t<DIM, Q>(a));
+        const T eu = T(ex) * u0 + T(ey) * u1 + T(ez) * u2;
+        const T eF = T(ex) * F0 + T(ey) * F1 + T(ez) * F2;
+        const T poly = c1 * eu + c2 * eu * eu - c3 * uu;
+        // equilibrium (Eq. geq_s), as a deviation from t rho0 when DEV
+        const T feq = DEV ? t * (m0 + rho * poly) : t * rho * (T(1) + poly);
+        // higher-order force (Eq. f_c): t ((e.u)(e.F)/cs4 - (u.F)/cs2)
+        const T fss = t * (T(9) * eu * eF - T(3) * uF);
+        const T fbeq = feq - half_dt * fss;
+        v[a] = v[a] - omega * (v[a] - fbeq) + dt * fss;
+    });
+    rho_out = rho;
+}
+
+// ----------------------------------------------------------- stage kernel --
+enum { M_STAGE1 = 0, M_STAGE23 = 1, M_LOCAL = 2, M_FILTER = 3 };
+
+template <typename T>
+struct StageArgs {
+    const T *op;     // operand state [Q][Gtot]
+    const T *f0in;   // post-collision state (stages 2, 3)
+    T *f0out;        // stage 1: post-collision state written here
+    T *rhoc;         // density at the collision [Gtot]
+    T *out;          // output state (interior nodes; all owned nodes for M_FILTER)
+    T *rtb;          // element contributions of boundary nodes [Q][E*NB]
+    T *local;        // M_LOCAL: element contributions [Q][E][NP]
+    const T *Gm, *invw, *D, *F;
+    const int32_t *pcode, *bmap, *ftag;
+    const uint8_t *bown;
+    const T *wallu;  // [ntags+1][3]
+    int64_t E, nblk, Gi, Gtot;
+    T dt, omega, rho0, ca, cb, cc;  // output = ca f0 + cb f_k + cc L(f_k)
+    T g[3];
+    T fsc[kMaxQ];  // F* per unit density: t_a (e_a . g) / cs2
+    int filter;    // M_STAGE1: filter the operand first
+};
+
+template <int DIM, int N, int Q, typename T, bool DEV, int MODE>
+__global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_stage(StageArgs<T> A)
+{
+    using GG = Geo<DIM, N>;
+    constexpr int n1 = GG::n1, NP = GG::NP, NI = GG::NI, NB = GG::NB, EPB = GG::EPB;
+    __shared__ T pl[3][EPB * NP];
+    __shared__ T sF[n1 * n1];
+
+    const int tid = threadIdx.x;
+    const int le = tid / NP;
+    const int p = tid - le * NP;
+    const int64_t eb = xcd_block(A.nblk);
+    if (eb >= A.nblk) return;  // whole workgroup
+    const int64_t e = eb * EPB + le;
+    const bool valid = e < A.E;
+    const bool filt = (MODE == M_FILTER) || (MODE == M_STAGE1 && A.filter);
+    if (filt) {
+        for (int q = tid; q < n1 * n1; q += GG::BLOCK) sF[q] = A.F[q];
+    }
+    const int i = p % n1;
+    const int j = (p / n1) % n1;
+    const int k = (DIM == 3) ? p / (n1 * n1) : 0;
+    const int pc = A.pcode[p];
+    const bool inner = pc >= 0;
+    const int bsl = inner ? 0 : -pc - 1;
+    int64_t gix = 0;
+    bool own = false;
+    if (valid) {
+        if (inner) {
+            gix = e * NI + pc;
+            own = true;
+        } else {
+            gix = A.Gi + A.bmap[e * NB + bsl];
+            own = A.bown[e * NB + bsl] != 0;
+        }
+    }
+    const int base = le * NP;
+
+    // operand values of the node, all velocities
+    T fq[Q];
+    static_for<0, Q>([&](auto AA) {
+        constexpr int a = decltype(AA)::value;
+        fq[a] = valid ? A.op[(int64_t)a * A.Gtot + gix] : T(0);
+    });
+
+    if (filt) __syncthreads();  // sF visible
+    if (filt) {
+        // explicit modal filter (Sec. 2.2.3): (F x F x F) applied one direction at a time
+        static_for<0, Q>([&](auto AA) {
+            constexpr int a = decltype(AA)::value;
+            pl[0][base + p] = fq[a];
+            __syncthreads();
+            T t1 = 0;
+#pragma unroll
+            for (int c = 0; c < n1; ++c) t1 += sF[i * n1 + c] * pl[0][base + c + n1 * j + n1 * n1 * k];
+            pl[1][base + p] = t1;
+            __syncthreads();
+            T t2 = 0;
+#pragma unroll
+            for (int c = 0; c < n1; ++c) t2 += sF[j * n1 + c] * pl[1][base + i + n1 * c + n1 * n1 * k];
+            if constexpr (DIM == 3) {
+                pl[2][base + p] = t2;
+                __syncthreads();
+                T t3 = 0;
+#pragma unroll
+                for (int c = 0; c < n1; ++c) t3 += sF[k * n1 + c] * pl[2][base + i + n1 * j + n1 * n1 * c];
+                fq[a] = t3;
+            } else {
+                fq[a] = t2;
+            }
+        });
+        if (MODE == M_FILTER) {
+            if (valid && own) {
+                static_for<0, Q>([&](auto AA) {
+                    constexpr int a = decltype(AA)::value;
+                    A.out[(int64_t)a * A.Gtot + gix] = fq[a];
+                });
+            }
+            return;
+        }
+    }
+
+    T rho = 0;
+    if (MODE == M_STAGE1) {
+        if (valid) {
+            collide_node<DIM, Q, T, DEV>(fq, A.rho0, A.omega, A.dt, A.g, rho);
+            if (own) {
+                static_for<0, Q>([&](auto AA) {
+                    constexpr int a = decltype(AA)::value;
+                    A.f0out[(int64_t)a * A.Gtot + gix] = fq[a];
+                });
+                A.rhoc[gix] = rho;
+            }
+        }
+    } else if (MODE == M_STAGE23) {
+        if (valid && inner) rho = A.rhoc[gix];
+    }
+
+    // D-hat rows of this node and its metric terms
+    T Di[n1], Dj[n1], Dk[n1];
+#pragma unroll
+    for (int c = 0; c < n1; ++c) {
+        Di[c] = A.D[i * n1 + c];
+        Dj[c] = A.D[j * n1 + c];
+        Dk[c] = (DIM == 3) ? A.D[k * n1 + c] : T(0);
+    }
+    T Gr[DIM][DIM];
+#pragma unroll
+    for (int m = 0; m < DIM; ++m)
+#pragma unroll
+        for (int q = 0; q < DIM; ++q) Gr[m][q] = valid ? A.Gm[(e * DIM * DIM + m * DIM + q) * NP + p] : T(0);
+    T invw = 0;
+    if (valid && inner && MODE != M_LOCAL) invw = A.invw[e * NI + pc];
+
+    // wall faces through this node (flux bounce-back, Sec. 2.2.1): outward
+    // area vector w_s J_s n = +-(w_end)^-1 wJ dr_m/dx on face r_m = +-1
+    int nw = 0;
+    T wA[DIM][3];
+    T wub[DIM][3];
+    if (valid && !inner) {
+        const int idx[3] = {i, j, k};
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) {
+            if (idx[m] == 0 || idx[m] == N) {
+                const int fc = 2 * m + (idx[m] == N ? 1 : 0);
+                const int tag = A.ftag[e * 2 * DIM + fc];
+                if (tag > 0) {
+                    const T sc = (idx[m] == N ? T(1) : T(-1)) * T(N * (N + 1)) / T(2);
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        wA[nw][q] = (q < DIM) ? sc * Gr[m][q] : T(0);
+                        wub[nw][q] = A.wallu[tag * 3 + q];
+                    }
+                    ++nw;
+                }
+            }
+        }
+    }
+
+    // streaming operator per velocity (Sec. 2.2): rt = -wJ e . grad f (+ wall flux)
+    static_for<0, Q>([&](auto AA) {
+        constexpr int a = decltype(AA)::value;
+        constexpr int ex = lat_e<DIM, Q>(a, 0), ey = lat_e<DIM, Q>(a, 1), ez = lat_e<DIM, Q>(a, 2);
+        T *P = pl[a & 1];
+        P[base + p] = fq[a];
+        __syncthreads();
+        T dr = 0, ds = 0, dtt = 0;
+#pragma unroll
+        for (int c = 0; c < n1; ++c) dr += Di[c] * P[base + c + n1 * j + n1 * n1 * k];
+#pragma unroll
+        for (int c = 0; c < n1; ++c) ds += Dj[c] * P[base + i + n1 * c + n1 * n1 * k];
+        if constexpr (DIM == 3) {
+#pragma unroll
+            for (int c = 0; c < n1; ++c) dtt += Dk[c] * P[base + i + n1 * j + n1 * n1 * c];
+        }
+        // c_m = sum_k e_k G_mk
+        T cr = 0, cs = 0, ct = 0;
+        if constexpr (ex != 0) {
+            cr += T(ex) * Gr[0][0];
+            cs += T(ex) * Gr[1][0];
+            if constexpr (DIM == 3) ct += T(ex) * Gr[2][0];
+        }
+        if constexpr (ey != 0) {
+            cr += T(ey) * Gr[0][1];
+            cs += T(ey) * Gr[1][1];
+            if constexpr (DIM == 3) ct += T(ey) * Gr[2][1];
+        }
+        if constexpr (DIM == 3 && ez != 0) {
+            cr += T(ez) * Gr[0][2];
+            cs += T(ez) * Gr[1][2];
+            ct += T(ez) * Gr[2][2];
+        }
+        T rt = -(cr * dr + cs * ds + ct * dtt);
+        if (nw > 0) {
+            constexpr int b = lat_opp<DIM, Q>(a);
+            const T t = T(lat_t<DIM, Q>(a));
+#pragma unroll
+            for (int w = 0; w < DIM; ++w) {
+                if (w < nw) {
+                    const T ne = T(ex) * wA[w][0] + T(ey) * wA[w][1] + T(ez) * wA[w][2];
+                    if (ne < T(0)) {
+                        const T eub = T(ex) * wub[w][0] + T(ey) * wub[w][1] + T(ez) * wub[w][2];
+                        rt += ne * (fq[a] - fq[b] - T(2) * t * A.rho0 * eub * T(3));
+                    }
+                }
+            }
+        }
+        if (valid) {
+            if (MODE == M_LOCAL) {
+                A.local[((int64_t)a * A.E + e) * NP + p] = rt;
+            } else if (inner) {
+                const T L = rt * invw + A.fsc[a] * rho;
+                const T f0v = (MODE == M_STAGE1) ? fq[a] : A.f0in[(int64_t)a * A.Gtot + gix];
+                A.out[(int64_t)a * A.Gtot + gix] = A.ca * f0v + A.cb * fq[a] + A.cc * L;
+            } else {
+                A.rtb[(int64_t)a * (A.E * NB) + e * NB + bsl] = rt;
+            }
+        }
+    });
+}
+
+// -------------------------------------------------- boundary-node assembly --
+// Direct stiffness summation at shared nodes (continuous Galerkin): the
+// element contributions of a node group are summed in ascending member order,
+// scaled by the assembled inverse mass, F* is added and the Runge-Kutta
+// combination written once for the group.
+template <typename T>
+struct GroupArgs {
+    const T *rtb, *f0, *fk, *rhoc, *invMb;
+    T *out;
+    const int32_t *goff, *gmem;
+    int64_t ngrp, Gi, Gtot, EB;
+    T ca, cb, cc;
+    T fsc[kMaxQ];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_group(GroupArgs<T> A)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int a = blockIdx.y;
+    if (g >= A.ngrp) return;
+    const int j0 = A.goff[g], j1 = A.goff[g + 1];
+    const T *r = A.rtb + (int64_t)a * A.EB;
+    T s = 0;
+    for (int q = j0; q < j1; ++q) s += r[A.gmem[q]];
+    const int64_t ix = (int64_t)a * A.Gtot + A.Gi + g;
+    const T L = s * A.invMb[g] + A.fsc[a] * A.rhoc[A.Gi + g];
+    A.out[ix] = A.ca * A.f0[ix] + A.cb * A.fk[ix] + A.cc * L;
+}
+
+// ---------------------------------------------------------------- geometry --
+// Isoparametric geometry in FP64 (Sec. 2.2): dx/dr by D-hat on the node
+// coordinates, J = det, grad r_m = (a_{m+1} x a_{m+2}) / J with a_m = dx/dr_m
+// (2D: rotated tangents), wJ = w w w J, G_mk = wJ dr_m/dx_k.
+template <int DIM, int N, typename T>
+__global__ void __launch_bounds__((Geo<DIM, N>::BLOCK))
+    k_geom(const double *xyz, const double *D, const double *w, double *wJ, double *Jo, T *Gm, int32_t *flag,
+           int64_t E, int64_t nblk)
+{
+    using GG = Geo<DIM, N>;
+    constexpr int n1 = GG::n1, NP = GG::NP, EPB = GG::EPB;
+    __shared__ double sx[DIM][EPB * NP];
+    const int tid = threadIdx.x;
+    const int le = tid / NP, p = tid - le * NP;
+    const int64_t eb = blockIdx.x;
+    if (eb >= nblk) return;
+    const int64_t e = eb * EPB + le;
+    const bool valid = e < E;
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) sx[q][le * NP + p] = valid ? xyz[(e * NP + p) * DIM + q] : 0.0;
+    __syncthreads();
+    if (!valid) return;
+    const int idx[3] = {p % n1, (p / n1) % n1, DIM == 3 ? p / (n1 * n1) : 0};
+    const int str[3] = {1, n1, n1 * n1};
+    double a[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // a[m][q] = dx_q / dr_m
+    for (int m = 0; m < DIM; ++m) {
+        const int b0 = p - idx[m] * str[m];
+        for (int c = 0; c < n1; ++c) {
+            const double d = D[idx[m] * n1 + c];
+            for (int q = 0; q < DIM; ++q) a[m][q] += d * sx[q][le * NP + b0 + c * str[m]];
+        }
+    }
+    double J, gr[3][3];  // gr[m][q] = dr_m / dx_q
+    if (DIM == 2) {
+        J = a[0][0] * a[1][1] - a[0][1] * a[1][0];
+        gr[0][0] = a[1][1] / J;
+        gr[0][1] = -a[1][0] / J;
+        gr[1][0] = -a[0][1] / J;
+        gr[1][1] = a[0][0] / J;
+    } else {
+        double cx[3][3];
+        for (int m = 0; m < 3; ++m) {
+            const double *u = a[(m + 1) % 3], *v = a[(m + 2) % 3];
+            cx[m][0] = u[1] * v[2] - u[2] * v[1];
+            cx[m][1] = u[2] * v[0] - u[0] * v[2];
+            cx[m][2] = u[0] * v[1] - u[1] * v[0];
+        }
+        J = a[0][0] * cx[0][0] + a[0][1] * cx[0][1] + a[0][2] * cx[0][2];
+        for (int m = 0; m < 3; ++m)
+            for (int q = 0; q < 3; ++q) gr[m][q] = cx[m][q] / J;
+    }
+    double wp = w[idx[0]] * w[idx[1]];
+    if (DIM == 3) wp *= w[idx[2]];
+    const double wj = wp * J;
+    wJ[e * NP + p] = wj;
+    Jo[e * NP + p] = J;
+    for (int m = 0; m < DIM; ++m)
+        for (int q = 0; q < DIM; ++q) Gm[(e * DIM * DIM + m * DIM + q) * NP + p] = T(wj * gr[m][q]);
+    if (!(J > 0.0)) atomicOr(flag, 1);
+}
+
+// inverse lumped mass: interior nodes 1/wJ, boundary groups 1/sum of member wJ
+template <typename T>
+__global__ void k_mass_int(const double *wJ, const int32_t *pcode, T *invw, int64_t E, int NP, int NI)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= E * NP) return;
+    const int64_t e = q / NP;
+    const int p = (int)(q - e * NP);
+    const int pc = pcode[p];
+    if (pc >= 0) invw[e * NI + pc] = T(1.0 / wJ[q]);
+}
+template <typename T>
+__global__ void k_mass_grp(const double *wJ, const int32_t *bpos, const int32_t *goff, const int32_t *gmem,
+                           T *invMb, int64_t ngrp, int NP, int NB)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ngrp) return;
+    double s = 0.0;
+    for (int q = goff[g]; q < goff[g + 1]; ++q) {
+        const int64_t lb = gmem[q];
+        const int64_t e = lb / NB;
+        const int b = (int)(lb - e * NB);
+        s += wJ[e * NP + bpos[b]];
+    }
+    invMb[g] = T(1.0 / s);
+}
+
+// per-node helpers over local (element) nodes
+struct NodeMap {
+    const int32_t *pcode, *bmap;
+    const uint8_t *bown;
+    int64_t E, Gi;
+    int NP, NI, NB;
+    __device__ __forceinline__ int64_t gix(int64_t e, int p, bool &own) const
+    {
+        const int pc = pcode[p];
+        if (pc >= 0) {
+            own = true;
+            return e * NI + pc;
+        }
+        const int b = -pc - 1;
+        own = bown[e * NB + b] != 0;
+        return Gi + bmap[e * NB + b];
+    }
+};
+
+// f-bar = f^eq(rho, u) - dt F** / 2 (Sec. 2.1 with f = f^eq), computed in FP64
+template <int DIM, int Q, typename T, bool DEV>
+__global__ void k_init(NodeMap M, const double *rho, const double *u, T *f, int64_t Gtot, double rho0, double dt,
+                       double g0, double g1, double g2)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= M.E * M.NP) return;
+    const int64_t e = q / M.NP;
+    const int p = (int)(q - e * M.NP);
+    bool own;
+    const int64_t gi = M.gix(e, p, own);
+    if (!own) return;
+    const double r = rho[q];
+    double uu[3] = {0, 0, 0};
+    for (int c = 0; c < DIM; ++c) uu[c] = u[q * DIM + c];
+    const double F[3] = {r * g0, r * g1, r * g2};
+    const double u2 = uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2];
+    const double uF = uu[0] * F[0] + uu[1] * F[1] + uu[2] * F[2];
+    static_for<0, Q>([&](auto AA) {
+        constexpr int a = decltype(AA)::value;
+        const double ex = lat_e<DIM, Q>(a, 0), ey = lat_e<DIM, Q>(a, 1), ez = lat_e<DIM, Q>(a, 2);
+        const double t = lat_t<DIM, Q>(a);
+        const double eu = ex * uu[0] + ey * uu[1] + ez * uu[2];
+        const double eF = ex * F[0] + ey * F[1] + ez * F[2];
+        const double feq = t * r * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * u2);
+        const double fss = t * (9.0 * eu * eF - 3.0 * uF);
+        double v = feq - 0.5 * dt * fss;
+        if (DEV) v -= t * rho0;
+        f[(int64_t)a * Gtot + gi] = T(v);
+    });
+}
+
+// one velocity plane between the state and an FP64 element-node array
+template <typename T>
+__global__ void k_scatter_plane(NodeMap M, const double *src, T *dst, int64_t Gtot, int a, double off)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= M.E * M.NP) return;
+    const int64_t e = q / M.NP;
+    const int p = (int)(q - e * M.NP);
+    bool own;
+    const int64_t gi = M.gix(e, p, own);
+    if (own) dst[(int64_t)a * Gtot + gi] = T(src[q] - off);
+}
+template <typename T>
+__global__ void k_gather_plane(NodeMap M, const T *src, double *dst, int64_t Gtot, int a, double off)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= M.E * M.NP) return;
+    const int64_t e = q / M.NP;
+    const int p = (int)(q - e * M.NP);
+    bool own;
+    const int64_t gi = M.gix(e, p, own);
+    dst[q] = double(src[(int64_t)a * Gtot + gi]) + off;
+}
+
+// moments (Eqs. pressure, momentum) in FP64 at every element node
+template <int DIM, int Q, typename T, bool DEV>
+__global__ void k_moments(NodeMap M, const T *f, int64_t Gtot, double rho0, double *rho, double *u)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= M.E * M.NP) return;
+    const int64_t e = q / M.NP;
+    const int p = (int)(q - e * M.NP);
+    bool own;
+    const int64_t gi = M.gix(e, p, own);
+    double m = 0, j[3] = {0, 0, 0};
+    static_for<0, Q>([&](auto AA) {
+        constexpr int a = decltype(AA)::value;
+        const double v = double(f[(int64_t)a * Gtot + gi]);
+        m += v;
+        if constexpr (lat_e<DIM, Q>(a, 0) != 0) j[0] += lat_e<DIM, Q>(a, 0) * v;
+        if constexpr (lat_e<DIM, Q>(a, 1) != 0) j[1] += lat_e<DIM, Q>(a, 1) * v;
+        if constexpr (lat_e<DIM, Q>(a, 2) != 0) j[2] += lat_e<DIM, Q>(a, 2) * v;
+    });
+    const double r = DEV ? rho0 + m : m;
+    rho[q] = r;
+    for (int c = 0; c < DIM; ++c) u[q * DIM + c] = j[c] / r;
+}
+
+// FP64 integrals with the lumped mass and a non-finite count; per-block
+// partial sums in fixed order, summed by k_reduce_final.
+template <int DIM, int Q, typename T, bool DEV>
+__global__ void __launch_bounds__(256) k_reduce(NodeMap M, const T *f, int64_t Gtot, int Q_, const double *wJ,
+                                                double rho0, double *part)
+{
+    __shared__ double sh[8][256];
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int64_t nl = M.E * M.NP;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nl; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = q / M.NP;
+        const int p = (int)(q - e * M.NP);
+        bool own;
+        const int64_t gi = M.gix(e, p, own);
+        double m = 0, j[3] = {0, 0, 0};
+        static_for<0, Q>([&](auto AA) {
+            constexpr int a = decltype(AA)::value;
+            const double v = double(f[(int64_t)a * Gtot + gi]);
+            m += v;
+            if constexpr (lat_e<DIM, Q>(a, 0) != 0) j[0] += lat_e<DIM, Q>(a, 0) * v;
+            if constexpr (lat_e<DIM, Q>(a, 1) != 0) j[1] += lat_e<DIM, Q>(a, 1) * v;
+            if constexpr (lat_e<DIM, Q>(a, 2) != 0) j[2] += lat_e<DIM, Q>(a, 2) * v;
+        });
+        const double r = DEV ? rho0 + m : m;
+        const double wj = wJ[q];
+        acc[0] += wj * r;
+        double u2 = 0;
+        for (int c = 0; c < DIM; ++c) {
+            acc[1 + c] += wj * j[c];
+            u2 += (j[c] / r) * (j[c] / r);
+        }
+        acc[4] += wj * 0.5 * rho0 * u2;
+    }
+    const int64_t nv = (int64_t)Q_ * Gtot;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nv; q += (int64_t)gridDim.x * blockDim.x) {
+        const T v = f[q];
+        if (!(v == v) || v - v != T(0)) acc[5] += 1.0;
+    }
+    for (int c = 0; c < 8; ++c) sh[c][threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int c = 0; c < 8; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 8; ++c) part[blockIdx.x * 8 + c] = sh[c][0];
+}
+
+template <typename T>
+__global__ void k_reduce_final(const double *part, int nblk, double *out)
+{
+    if (threadIdx.x >= 8) return;
+    double s = 0;
+    for (int b = 0; b < nblk; ++b) s += part[b * 8 + threadIdx.x];
+    out[threadIdx.x] = s;
+}
+
+}  // namespace sel

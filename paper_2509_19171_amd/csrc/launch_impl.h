@@ -1,0 +1,311 @@
+// Launch sequences of the SELBM kernels for one (dim, N, Q, storage) choice.
+#pragma once
+
+#include "kernels_impl.h"
+#include "ops.h"
+
+namespace sel {
+
+#define SEL_LAUNCH_CHECK()                                                                  \
+    do {                                                                                    \
+        hipError_t err_ = hipGetLastError();                                                \
+        if (err_ != hipSuccess) {                                                           \
+            set_error(std::string("kernel launch failed: ") + hipGetErrorString(err_));    \
+            return SEL_EDEVICE;                                                             \
+        }                                                                                   \
+    } while (0)
+
+template <int DIM, int N, int Q, typename T, bool DEV>
+struct Impl {
+    using GG = Geo<DIM, N>;
+    static constexpr int NP = GG::NP, NI = GG::NI, NB = GG::NB, EPB = GG::EPB;
+
+    static T *st(sel_sim *s, int i) { return static_cast<T *>(s->f[i]); }
+    static int64_t nblk(sel_sim *s) { return (s->E + EPB - 1) / EPB; }
+
+    static NodeMap nodemap(sel_sim *s)
+    {
+        NodeMap M;
+        M.pcode = s->pcode;
+        M.bmap = s->bmap;
+        M.bown = s->bown;
+        M.E = s->E;
+        M.Gi = s->Gi;
+        M.NP = NP;
+        M.NI = NI;
+        M.NB = NB;
+        return M;
+    }
+
+    static StageArgs<T> stage_args(sel_sim *s)
+    {
+        StageArgs<T> A{};
+        A.Gm = static_cast<const T *>(s->Gm);
+        A.invw = static_cast<const T *>(s->invw);
+        A.D = static_cast<const T *>(s->tabD);
+        A.F = static_cast<const T *>(s->tabF);
+        A.pcode = s->pcode;
+        A.bmap = s->bmap;
+        A.ftag = s->ftag;
+        A.bown = s->bown;
+        A.wallu = static_cast<const T *>(s->wallu);
+        A.E = s->E;
+        A.nblk = nblk(s);
+        A.Gi = s->Gi;
+        A.Gtot = s->Gtot;
+        A.dt = T(s->p.dt);
+        A.omega = T(s->omega);
+        A.rho0 = T(s->p.rho0);
+        for (int q = 0; q < 3; ++q) A.g[q] = T(q < DIM ? s->p.accel[q] : 0.0);
+        for (int a = 0; a < Q; ++a) A.fsc[a] = T(s->fsc[a]);
+        A.rtb = static_cast<T *>(s->rtb);
+        A.rhoc = static_cast<T *>(s->rhoc);
+        return A;
+    }
+
+    static GroupArgs<T> group_args(sel_sim *s)
+    {
+        GroupArgs<T> B{};
+        B.rtb = static_cast<const T *>(s->rtb);
+        B.rhoc = static_cast<const T *>(s->rhoc);
+        B.invMb = static_cast<const T *>(s->invMb);
+        B.goff = s->goff;
+        B.gmem = s->gmem;
+        B.ngrp = s->ngrp;
+        B.Gi = s->Gi;
+        B.Gtot = s->Gtot;
+        B.EB = s->E * NB;
+        for (int a = 0; a < Q; ++a) B.fsc[a] = T(s->fsc[a]);
+        return B;
+    }
+
+    // events around a launch when sel_step_timed asked for them
+    static int tic(sel_sim *s, int kind, hipEvent_t &b)
+    {
+        if (!s->timing) return SEL_OK;
+        hipEvent_t e0, e1;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return SEL_EDEVICE;
+        s->timing->push_back({kind, {e0, e1}});
+        b = e1;
+        return hipEventRecord(e0, s->stream) == hipSuccess ? SEL_OK : SEL_EDEVICE;
+    }
+    static int toc(sel_sim *s, hipEvent_t b)
+    {
+        if (!s->timing) return SEL_OK;
+        return hipEventRecord(b, s->stream) == hipSuccess ? SEL_OK : SEL_EDEVICE;
+    }
+
+    template <int MODE>
+    static int launch_stage(sel_sim *s, const StageArgs<T> &A)
+    {
+        dim3 grid((unsigned)xcd_grid(A.nblk)), block(GG::BLOCK);
+        hipEvent_t ev = nullptr;
+        const int kind = (MODE == M_STAGE1) ? 0 : (MODE == M_STAGE23) ? 1 : 3;
+        if (int rc = tic(s, kind, ev)) return rc;
+        hipLaunchKernelGGL((k_stage<DIM, N, Q, T, DEV, MODE>), grid, block, 0, s->stream, A);
+        SEL_LAUNCH_CHECK();
+        return toc(s, ev);
+    }
+
+    static int launch_group(sel_sim *s, const GroupArgs<T> &B)
+    {
+        if (s->ngrp == 0) return SEL_OK;
+        dim3 grid((unsigned)((s->ngrp + 255) / 256), Q), block(256);
+        hipEvent_t ev = nullptr;
+        if (int rc = tic(s, 2, ev)) return rc;
+        hipLaunchKernelGGL((k_group<T>), grid, block, 0, s->stream, B);
+        SEL_LAUNCH_CHECK();
+        return toc(s, ev);
+    }
+
+    static int geometry(sel_sim *s)
+    {
+        const int64_t nb = nblk(s);
+        hipLaunchKernelGGL((k_geom<DIM, N, T>), dim3((unsigned)nb), dim3(GG::BLOCK), 0, s->stream, s->xyz,
+                           s->geoD, s->geoW, s->wJ, s->J, static_cast<T *>(s->Gm), s->flag, s->E, nb);
+        SEL_LAUNCH_CHECK();
+        return SEL_OK;
+    }
+
+    static int mass(sel_sim *s)
+    {
+        const int64_t nl = s->E * NP;
+        hipLaunchKernelGGL((k_mass_int<T>), dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, s->stream, s->wJ,
+                           s->pcode, static_cast<T *>(s->invw), s->E, NP, NI);
+        SEL_LAUNCH_CHECK();
+        if (s->ngrp > 0) {
+            hipLaunchKernelGGL((k_mass_grp<T>), dim3((unsigned)((s->ngrp + 255) / 256)), dim3(256), 0, s->stream,
+                               s->wJ, s->bpos, s->goff, s->gmem, static_cast<T *>(s->invMb), s->ngrp, NP, NB);
+            SEL_LAUNCH_CHECK();
+        }
+        return SEL_OK;
+    }
+
+    static int init(sel_sim *s, const double *d_rho, const double *d_u)
+    {
+        const int64_t nl = s->E * NP;
+        hipLaunchKernelGGL((k_init<DIM, Q, T, DEV>), dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, s->stream,
+                           nodemap(s), d_rho, d_u, st(s, s->cur), s->Gtot, s->p.rho0, s->p.dt, s->p.accel[0],
+                           s->p.accel[1], DIM == 3 ? s->p.accel[2] : 0.0);
+        SEL_LAUNCH_CHECK();
+        return SEL_OK;
+    }
+
+    // one time step: collide (and filter the previous step's result) ->
+    // SSPRK3 streaming with F* and the wall flux; the filter of this step is
+    // applied by the next step's first stage, or at the end of the call.
+    static int step(sel_sim *s, int64_t nsteps)
+    {
+        if (nsteps <= 0) return SEL_OK;
+        const double dt = s->p.dt;
+        const bool filt = s->p.filter_type != SEL_FILTER_NONE;
+        StageArgs<T> A = stage_args(s);
+        GroupArgs<T> B = group_args(s);
+        T *F0 = st(s, 2), *FA = st(s, 3);
+        bool pending = false;
+        for (int64_t n = 0; n < nsteps; ++n) {
+            T *S = st(s, s->cur), *FB = st(s, s->cur ^ 1);
+            // stage 1: f1 = f0 + dt L(f0), f0 = collide(filter(f3_prev) or f-bar)
+            A.op = S;
+            A.f0out = F0;
+            A.out = FA;
+            A.ca = T(0);
+            A.cb = T(1);
+            A.cc = T(dt);
+            A.filter = pending ? 1 : 0;
+            if (int rc = launch_stage<M_STAGE1>(s, A)) return rc;
+            B.f0 = F0;
+            B.fk = F0;
+            B.out = FA;
+            B.ca = T(0);
+            B.cb = T(1);
+            B.cc = T(dt);
+            if (int rc = launch_group(s, B)) return rc;
+            // stage 2: f2 = 3/4 f0 + 1/4 (f1 + dt L(f1))
+            A.op = FA;
+            A.f0in = F0;
+            A.out = FB;
+            A.ca = T(0.75);
+            A.cb = T(0.25);
+            A.cc = T(0.25 * dt);
+            if (int rc = launch_stage<M_STAGE23>(s, A)) return rc;
+            B.fk = FA;
+            B.out = FB;
+            B.ca = T(0.75);
+            B.cb = T(0.25);
+            B.cc = T(0.25 * dt);
+            if (int rc = launch_group(s, B)) return rc;
+            // stage 3: f3 = 1/3 f0 + 2/3 (f2 + dt L(f2)), written over the state
+            A.op = FB;
+            A.out = S;
+            A.ca = T(1.0 / 3.0);
+            A.cb = T(2.0 / 3.0);
+            A.cc = T(2.0 / 3.0 * dt);
+            if (int rc = launch_stage<M_STAGE23>(s, A)) return rc;
+            B.fk = FB;
+            B.out = S;
+            B.ca = T(1.0 / 3.0);
+            B.cb = T(2.0 / 3.0);
+            B.cc = T(2.0 / 3.0 * dt);
+            if (int rc = launch_group(s, B)) return rc;
+            pending = filt;
+            s->time += dt;
+            s->nstep += 1;
+        }
+        if (pending) {
+            A.op = st(s, s->cur);
+            A.out = st(s, s->cur ^ 1);
+            if (int rc = launch_stage<M_FILTER>(s, A)) return rc;
+            s->cur ^= 1;
+        }
+        return SEL_OK;
+    }
+
+    static int moments(sel_sim *s, double *d_rho, double *d_u)
+    {
+        const int64_t nl = s->E * NP;
+        hipLaunchKernelGGL((k_moments<DIM, Q, T, DEV>), dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, s->stream,
+                           nodemap(s), st(s, s->cur), s->Gtot, s->p.rho0, d_rho, d_u);
+        SEL_LAUNCH_CHECK();
+        return SEL_OK;
+    }
+
+    static int reduce(sel_sim *s)
+    {
+        hipLaunchKernelGGL((k_reduce<DIM, Q, T, DEV>), dim3(s->nred), dim3(256), 0, s->stream, nodemap(s),
+                           st(s, s->cur), s->Gtot, Q, s->wJ, s->p.rho0, s->red);
+        SEL_LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_reduce_final<T>), dim3(1), dim3(64), 0, s->stream, s->red, s->nred, s->red + 8 * s->nred);
+        SEL_LAUNCH_CHECK();
+        return SEL_OK;
+    }
+
+    static int scatter(sel_sim *s, int a, const double *d_plane, void *dst, bool sub)
+    {
+        const int64_t nl = s->E * NP;
+        hipLaunchKernelGGL((k_scatter_plane<T>), dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, s->stream,
+                           nodemap(s), d_plane, static_cast<T *>(dst), s->Gtot, a, sub ? s->toff[a] : 0.0);
+        SEL_LAUNCH_CHECK();
+        return SEL_OK;
+    }
+
+    static int gather(sel_sim *s, int a, const void *src, double *d_plane, bool add)
+    {
+        const int64_t nl = s->E * NP;
+        hipLaunchKernelGGL((k_gather_plane<T>), dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, s->stream,
+                           nodemap(s), static_cast<const T *>(src), d_plane, s->Gtot, a, add ? s->toff[a] : 0.0);
+        SEL_LAUNCH_CHECK();
+        return SEL_OK;
+    }
+
+    // operator pieces on a state in src (scratch arrays only)
+    static int apply(sel_sim *s, int op, void *src_v, void *dst_v, void *local_v)
+    {
+        T *src = static_cast<T *>(src_v), *dst = static_cast<T *>(dst_v);
+        StageArgs<T> A = stage_args(s);
+        A.op = src;
+        if (op == SEL_OP_RHS || op == SEL_OP_RHS_LOCAL) {
+            for (int a = 0; a < Q; ++a) A.fsc[a] = T(0);
+            if (hipMemsetAsync(s->rhoc, 0, sizeof(T) * s->Gtot, s->stream) != hipSuccess) return SEL_EDEVICE;
+            if (op == SEL_OP_RHS_LOCAL) {
+                A.local = static_cast<T *>(local_v);
+                return launch_stage<M_LOCAL>(s, A);
+            }
+            A.f0in = src;
+            A.out = dst;
+            A.ca = T(0);
+            A.cb = T(0);
+            A.cc = T(1);
+            if (int rc = launch_stage<M_STAGE23>(s, A)) return rc;
+            GroupArgs<T> B = group_args(s);
+            for (int a = 0; a < Q; ++a) B.fsc[a] = T(0);
+            B.f0 = src;
+            B.fk = src;
+            B.out = dst;
+            B.ca = T(0);
+            B.cb = T(0);
+            B.cc = T(1);
+            return launch_group(s, B);
+        }
+        if (op == SEL_OP_COLLIDE) {
+            A.f0out = dst;
+            A.out = st(s, s->cur ^ 1);
+            A.filter = 0;
+            A.ca = A.cb = A.cc = T(0);
+            return launch_stage<M_STAGE1>(s, A);
+        }
+        if (op == SEL_OP_FILTER) {
+            A.out = dst;
+            return launch_stage<M_FILTER>(s, A);
+        }
+        return SEL_EINVAL;
+    }
+
+    static const Ops *ops()
+    {
+        static const Ops o = {geometry, mass, init, step, moments, reduce, scatter, gather, apply};
+        return &o;
+    }
+};
+
+}  // namespace sel

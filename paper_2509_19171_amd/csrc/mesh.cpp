@@ -1,0 +1,184 @@
+// Mesh ingest: validation, structural node classes and the shared-node
+// groups of the continuous-Galerkin assembly.
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <numeric>
+
+#include "sel_internal.h"
+
+using sel::set_error;
+
+static int ipow(int b, int e)
+{
+    int r = 1;
+    for (int i = 0; i < e; ++i) r *= b;
+    return r;
+}
+
+extern "C" int sel_mesh_create(int32_t dim, int32_t N, int64_t E, const double *xyz, const int64_t *gid,
+                               const int32_t *face_tag, int32_t ntags, const double *wall_u, sel_mesh **out)
+{
+    if (!out || !xyz || !gid) {
+        set_error("sel_mesh_create: null pointer argument");
+        return SEL_EINVAL;
+    }
+    if (dim != 2 && dim != 3) {
+        set_error("sel_mesh_create: dim must be 2 or 3");
+        return SEL_EINVAL;
+    }
+    if (N < 2 || N + 1 > sel::kMaxN1) {
+        set_error("sel_mesh_create: order N must be in [2, 15]");
+        return SEL_EUNSUPPORTED;
+    }
+    if (E < 1) {
+        set_error("sel_mesh_create: E must be >= 1");
+        return SEL_EINVAL;
+    }
+    if (ntags < 0 || (ntags > 0 && !wall_u)) {
+        set_error("sel_mesh_create: ntags < 0 or wall_u missing");
+        return SEL_EINVAL;
+    }
+    sel_mesh *m = new (std::nothrow) sel_mesh();
+    if (!m) {
+        set_error("sel_mesh_create: out of host memory");
+        return SEL_ENOMEM;
+    }
+    try {
+        m->dim = dim;
+        m->N = N;
+        m->n1 = N + 1;
+        m->np = ipow(N + 1, dim);
+        m->nint = ipow(N - 1, dim);
+        m->nbe = m->np - m->nint;
+        m->nface = 2 * dim;
+        m->E = E;
+        const int64_t nl = E * (int64_t)m->np;
+        if (E * (int64_t)m->nbe > INT32_MAX || nl > INT32_MAX) {
+            set_error("sel_mesh_create: mesh too large for 32-bit node indices");
+            delete m;
+            return SEL_EUNSUPPORTED;
+        }
+        m->xyz.assign(xyz, xyz + nl * dim);
+        m->gid.assign(gid, gid + nl);
+        m->ftag.assign((size_t)E * m->nface, 0);
+        if (face_tag)
+            for (int64_t i = 0; i < E * m->nface; ++i) {
+                if (face_tag[i] < 0 || face_tag[i] > ntags) {
+                    set_error("sel_mesh_create: face_tag out of [0, ntags]");
+                    delete m;
+                    return SEL_EINVAL;
+                }
+                m->ftag[i] = face_tag[i];
+            }
+        m->ntags = ntags;
+        m->wall_u.assign((size_t)(ntags + 1) * 3, 0.0);
+        for (int t = 0; t < ntags; ++t)
+            for (int k = 0; k < dim; ++k) m->wall_u[3 * (t + 1) + k] = wall_u[t * dim + k];
+        m->nwall = 0;
+        for (int32_t v : m->ftag) m->nwall += (v > 0);
+
+        // structural classes: interior nodes (no index at 0 or N) and boundary slots
+        m->pcode.resize(m->np);
+        m->bpos.resize(m->nbe);
+        int ns = 0, nb = 0;
+        for (int p = 0; p < m->np; ++p) {
+            int ijk[3] = {p % m->n1, (p / m->n1) % m->n1, dim == 3 ? p / (m->n1 * m->n1) : 1};
+            bool inner = true;
+            for (int d = 0; d < dim; ++d) inner = inner && ijk[d] > 0 && ijk[d] < N;
+            if (inner) {
+                m->pcode[p] = ns++;
+            } else {
+                m->bpos[nb] = p;
+                m->pcode[p] = -(nb + 1);
+                ++nb;
+            }
+        }
+
+        // global ids: range check and no sharing of interior nodes
+        std::vector<int32_t> cnt((size_t)nl, 0);
+        for (int64_t i = 0; i < nl; ++i) {
+            if (gid[i] < 0 || gid[i] >= nl) {
+                set_error("sel_mesh_create: gid out of [0, E*np)");
+                delete m;
+                return SEL_EINVAL;
+            }
+            cnt[gid[i]]++;
+        }
+        for (int64_t e = 0; e < E; ++e)
+            for (int p = 0; p < m->np; ++p)
+                if (m->pcode[p] >= 0 && cnt[gid[e * m->np + p]] != 1) {
+                    set_error("sel_mesh_create: a node off the element faces is shared");
+                    delete m;
+                    return SEL_EINVAL;
+                }
+
+        // shared-node groups over element-boundary nodes, members ascending,
+        // groups ordered by their first member (the owner)
+        const int64_t nlb = E * (int64_t)m->nbe;
+        std::vector<std::pair<int64_t, int32_t>> key((size_t)nlb);
+        for (int64_t e = 0; e < E; ++e)
+            for (int b = 0; b < m->nbe; ++b) {
+                int64_t lb = e * m->nbe + b;
+                key[lb] = {gid[e * m->np + m->bpos[b]], (int32_t)lb};
+            }
+        std::sort(key.begin(), key.end());
+        std::vector<int64_t> run_start;
+        for (int64_t i = 0; i < nlb; ++i)
+            if (i == 0 || key[i].first != key[i - 1].first) run_start.push_back(i);
+        run_start.push_back(nlb);
+        const int64_t ngrp = (int64_t)run_start.size() - 1;
+        std::vector<int64_t> order((size_t)ngrp);
+        std::iota(order.begin(), order.end(), 0);
+        std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+            return key[run_start[a]].second < key[run_start[b]].second;
+        });
+        m->ngrp = ngrp;
+        m->goff.resize(ngrp + 1);
+        m->gmem.resize(nlb);
+        m->bmap.resize(nlb);
+        m->bown.assign(nlb, 0);
+        int64_t pos = 0;
+        for (int64_t g = 0; g < ngrp; ++g) {
+            int64_t r = order[g];
+            m->goff[g] = (int32_t)pos;
+            for (int64_t i = run_start[r]; i < run_start[r + 1]; ++i) {
+                int32_t lb = key[i].second;
+                m->gmem[pos++] = lb;
+                m->bmap[lb] = (int32_t)g;
+            }
+            m->bown[m->gmem[m->goff[g]]] = 1;
+        }
+        m->goff[ngrp] = (int32_t)pos;
+        m->unique_nodes = E * (int64_t)m->nint + ngrp;
+    } catch (const std::bad_alloc &) {
+        set_error("sel_mesh_create: out of host memory");
+        delete m;
+        return SEL_ENOMEM;
+    }
+    *out = m;
+    return SEL_OK;
+}
+
+extern "C" int sel_mesh_destroy(sel_mesh *mesh)
+{
+    delete mesh;
+    return SEL_OK;
+}
+
+extern "C" int sel_mesh_info(const sel_mesh *m, int64_t *info)
+{
+    if (!m || !info) {
+        set_error("sel_mesh_info: null pointer argument");
+        return SEL_EINVAL;
+    }
+    info[0] = m->dim;
+    info[1] = m->N;
+    info[2] = m->E;
+    info[3] = m->np;
+    info[4] = m->unique_nodes;
+    info[5] = m->ngrp;
+    info[6] = m->nbe;
+    info[7] = m->nwall;
+    return SEL_OK;
+}

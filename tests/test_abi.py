@@ -1,0 +1,100 @@
+"""CPU checks of the C interface: the library loads, exports every function
+that include/sel.h declares, and its host-side mesh ingest validates input
+(no device call is made here)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+from paper_2509_19171_amd import inputs as I
+from paper_2509_19171_amd import sel
+
+HEADER = os.path.join(ROOT, "include", "sel.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(sel_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol():
+    lib = sel.load()
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    # and nothing of the oracle is linked in
+    assert not hasattr(lib, "oracle_step")
+    assert "gfx950" in sel.version()
+
+
+def test_mesh_ingest_groups():
+    m = I.box_mesh(2, 3, (4, 3), (0, 0), (1, 1), (True, False), wall_tags={1: (1, 2)},
+                   wall_u=[[0, 0], [0.1, 0]])
+    sm = sel.Mesh.from_inputs(m)
+    info = sm.info()
+    assert info["np"] == 16 and info["E"] == 12
+    assert info["boundary_nodes_per_element"] == 16 - 4
+    # unique nodes of a 4x3 element periodic-in-x channel at N = 3: (4*3) x (3*3 + 1)
+    assert info["unique_nodes"] == len(np.unique(m.gid)) == 12 * 10
+    assert info["wall_faces"] == 8
+
+
+def test_mesh_ingest_rejects_bad_input():
+    m = I.box_mesh(2, 3, (2, 2), (0, 0), (1, 1), (True, True))
+    gid = m.gid.copy()
+    gid[0, 5] = gid[1, 5]  # share an interior node
+    with pytest.raises(sel.SelError) as ex:
+        sel.Mesh(2, 3, m.xyz, gid, m.face_tag)
+    assert ex.value.code == sel.SEL_EINVAL
+    gid = m.gid.copy()
+    gid[0, 0] = m.E * m.np_  # out of range
+    with pytest.raises(sel.SelError):
+        sel.Mesh(2, 3, m.xyz, gid, m.face_tag)
+    ft = m.face_tag.copy()
+    ft[0, 0] = 3  # tag beyond ntags
+    with pytest.raises(sel.SelError):
+        sel.Mesh(2, 3, m.xyz, m.gid, ft)
+    with pytest.raises(sel.SelError) as ex:
+        sel.Mesh(4, 3, m.xyz, m.gid, m.face_tag)
+    assert ex.value.code == sel.SEL_EINVAL
+    with pytest.raises(sel.SelError) as ex:
+        sel.Mesh(2, 1, m.xyz, m.gid, m.face_tag)
+    assert ex.value.code == sel.SEL_EUNSUPPORTED
+
+
+def test_workspace_bytes_and_param_checks():
+    c = I.case_tgv3d(nel=2, N=7, steps=0)
+    sm = sel.Mesh.from_inputs(c.mesh)
+    p64 = sel.params_from_case(c, "fp64")
+    p32 = sel.params_from_case(c, "fp32dev")
+    b64 = sm.workspace_bytes(p64)
+    b32 = sm.workspace_bytes(p32)
+    info = sm.info()
+    G = info["unique_nodes"]
+    assert b64 > 4 * 27 * G * 8 and b32 > 4 * 27 * G * 4 and b32 < b64
+    bad = sel.params_from_case(c, "fp64")
+    bad.Q = 9
+    with pytest.raises(sel.SelError):
+        sm.workspace_bytes(bad)
+    bad = sel.params_from_case(c, "fp64")
+    bad.nu = -1.0
+    with pytest.raises(sel.SelError):
+        sm.workspace_bytes(bad)
+    bad = sel.params_from_case(c, "fp64")
+    bad.filter_kc = 7
+    with pytest.raises(sel.SelError):
+        sm.workspace_bytes(bad)
+    msg = sel.load().sel_last_error().decode()
+    assert "filter_kc" in msg
+
+
+def test_binding_refuses_missing_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(sel, "_lib", None)
+    monkeypatch.setattr(sel, "LIB_PATH", str(tmp_path / "libsel.so"))
+    with pytest.raises(RuntimeError):
+        sel.load()

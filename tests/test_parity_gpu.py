@@ -1,0 +1,264 @@
+"""GPU parity: the HIP library (through the C interface) against the FP64 CPU
+oracle on the same seeded inputs.
+
+Tolerances (normwise relative error max|a - b| / max|b|):
+  FP64 storage: 1e-12 on f, rho, u and the geometry (single operators and
+  whole runs); velocities are normalised by max(max|u|, 0.01 c_s), since a
+  flow started from rest carries the absolute round-off of the O(1)
+  distribution (summation order differs between the two sides);
+  FP32 deviation storage: 1e-5 on rho and u after 200 steps, 2e-6 on
+  single operators (FP32 rounding of O(1) quantities, eps_32 = 6e-8, times
+  the conditioning of the collocation derivative, ~N^2).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from conftest import nerr
+from paper_2509_19171_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+CS = 3 ** -0.5
+
+
+def uerr(u, uref):
+    """Velocity error normalised by max(max|u_ref|, 0.01 c_s)."""
+    return float(np.abs(u - uref).max() / max(np.abs(uref).max(), 0.01 * CS))
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu_ready():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    from paper_2509_19171_amd import sel
+
+    sel.load()
+    yield
+
+
+def _sel():
+    from paper_2509_19171_amd import sel
+
+    return sel
+
+
+def _oracle(case, **kw):
+    import oracle
+
+    return oracle.from_case(case, **kw)
+
+
+def _cases_small():
+    """Small meshes spanning several workgroups and a ragged tail."""
+    out = {}
+    c = I.case_tgv2d(nel=5, N=5, steps=0, filt="quad")
+    c.mesh = I.box_mesh(2, 5, (5, 3), (0, 0), (2 * math.pi, 2 * math.pi), (True, True))
+    c.rho, c.u = I.tgv2d_fields(c.mesh.xyz, 0.05)
+    out["tgv2d_ragged_N5"] = c
+    out["channel_curved_N7"] = I.case_couette(nelx=4, nely=3, N=7, curved=True, filt="exp")
+    out["poiseuille_curved_N6"] = I.case_poiseuille(nelx=3, nely=2, N=6, curved=True)
+    c3 = I.case_tgv3d(nel=3, N=4, Q=27, Re=200.0, steps=0, filt="quad")
+    out["tgv3d_q27_N4"] = c3
+    # 3D box with FBB walls in z (moving top) and D3Q19
+    m = I.box_mesh(3, 3, (2, 3, 2), (0, 0, 0), (1, 1.5, 1), (True, True, False), wall_tags={2: (1, 2)},
+                   wall_u=[[0, 0, 0], [0.03, 0.01, 0]])
+    rho, u = I.rest_fields(m.xyz)
+    out["box3d_q19_walls_N3"] = I.Case("box3d_q19", m, 19, 1.0, 0.01, I.stable_dt(m), rho, u, 0,
+                                      g=(1e-3, 0.0, 0.0), filter="quad", filter_kc=2, filter_amp=0.1)
+    # a single periodic element (every face node shared with the element itself)
+    m1 = I.box_mesh(2, 6, (1, 1), (0, 0), (2 * math.pi, 2 * math.pi), (True, True))
+    r1, u1 = I.tgv2d_fields(m1.xyz, 0.05)
+    out["single_element_N6"] = I.Case("single", m1, 9, 1.0, 0.01, I.stable_dt(m1), r1, u1, 0)
+    return out
+
+
+CASES = _cases_small()
+
+
+def _random_f(case, seed=3, amp=1e-2):
+    """A continuous (per global node) perturbed equilibrium-like state."""
+    import oracle
+
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ng = int(case.gid.max()) + 1
+    e, t, _ = oracle.lattice(case.dim, case.Q)
+    base = t[None, :] * (1.0 + amp * rng.standard_normal((ng, case.Q)))
+    return base[case.gid].transpose(0, 2, 1).copy()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_geometry_parity(name):
+    c = CASES[name]
+    say(f"geometry {name}")
+    sim = _sel().from_case(c, "fp64")
+    o = _oracle(c)
+    wJ, J = sim.geometry()
+    owJ, _, oJ = o.geometry()
+    assert nerr(wJ, owJ) < 1e-12
+    assert nerr(J, oJ) < 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32dev", 2e-6)])
+@pytest.mark.parametrize("op", ["rhs_local", "rhs", "collide", "filter"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_operator_parity(name, op, prec, tol):
+    c = CASES[name]
+    say(f"operator {op} {prec} {name}")
+    sim = _sel().from_case(c, prec)
+    o = _oracle(c)
+    f = _random_f(c)
+    got = sim.apply(op, f)
+    ref = {"rhs_local": o.rhs_local, "rhs": o.rhs, "collide": o.collide, "filter": o.filter}[op](f)
+    if op in ("rhs_local", "rhs"):
+        # operators of differences: scale by the operand's variation
+        err = np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300)
+    else:
+        err = nerr(got, ref)
+    assert err < tol, err
+
+
+@pytest.mark.parametrize("name,steps", [("tgv2d_ragged_N5", 200), ("channel_curved_N7", 200),
+                                        ("poiseuille_curved_N6", 200), ("tgv3d_q27_N4", 40),
+                                        ("box3d_q19_walls_N3", 60), ("single_element_N6", 100)])
+def test_step_parity_fp64(name, steps):
+    c = CASES[name]
+    say(f"steps fp64 {name} x{steps}")
+    sim = _sel().from_case(c, "fp64")
+    o = _oracle(c)
+    sim.step(steps)
+    o.step(steps)
+    rho, u = sim.moments()
+    orho, ou = o.moments()
+    assert nerr(rho, orho) < 1e-12
+    assert uerr(u, ou) < 1e-12
+    assert nerr(sim.get_f(), o.get_f()) < 1e-12
+    assert abs(sim.time - o.time) < 1e-12 * o.time
+
+
+@pytest.mark.parametrize("name,steps", [("tgv2d_ragged_N5", 200), ("channel_curved_N7", 200),
+                                        ("tgv3d_q27_N4", 200), ("box3d_q19_walls_N3", 200)])
+def test_step_parity_fp32dev(name, steps):
+    c = CASES[name]
+    say(f"steps fp32dev {name} x{steps}")
+    sim = _sel().from_case(c, "fp32dev")
+    o = _oracle(c)
+    sim.step(steps)
+    o.step(steps)
+    rho, u = sim.moments()
+    orho, ou = o.moments()
+    er, eu = nerr(rho, orho), nerr(u, ou)
+    say(f"  fp32dev error rho {er:.3e} u {eu:.3e}")
+    assert er < 1e-5
+    assert eu < 1e-5
+
+
+def test_config0_tgv2d_fp64_and_fp32():
+    """The 2D Taylor-Green workload at full size (8x8, N = 5, 200 steps)."""
+    c = I.case_tgv2d(filt="quad")
+    say("tgv2d 8x8 N5 200 steps")
+    o = _oracle(c)
+    o.step(200)
+    orho, ou = o.moments()
+    for prec, tol in (("fp64", 1e-12), ("fp32dev", 1e-5)):
+        sim = _sel().from_case(c, prec)
+        sim.step(200)
+        rho, u = sim.moments()
+        assert nerr(rho, orho) < tol and nerr(u, ou) < tol, prec
+
+
+def test_full_size_tgv3d_parity():
+    """The benchmark workload (16^3 hexes, N = 7, D3Q27) in the benchmark's
+    launch configuration: whole-field parity after 2 steps."""
+    c = I.case_tgv3d(steps=0)
+    say("tgv3d 16^3 N7 D3Q27: oracle 2 steps")
+    o = _oracle(c)
+    o.step(2)
+    orho, ou = o.moments()
+    of = o.get_f()
+    m0 = o.reduce()[0]
+    del o
+    for prec, tol in (("fp64", 1e-12), ("fp32dev", 2e-6)):
+        say(f"tgv3d full size {prec}")
+        sim = _sel().from_case(c, prec)
+        sim.step(2)
+        rho, u = sim.moments()
+        assert nerr(rho, orho) < tol, prec
+        assert nerr(u, ou) < tol, prec
+        if prec == "fp64":
+            assert nerr(sim.get_f(), of) < 1e-12
+        red = sim.reduce()
+        assert abs(red[0] - m0) < 1e-6 * m0 and red[-1] == 0
+        del sim
+        torch.cuda.empty_cache()
+
+
+def test_determinism_and_checkpoint():
+    c = CASES["channel_curved_N7"]
+    say("determinism/checkpoint")
+    s1 = _sel().from_case(c, "fp64")
+    s1.step(30)
+    f30 = s1.get_f()
+    s1.step(30)
+    f60 = s1.get_f()
+    s2 = _sel().from_case(c, "fp64")
+    s2.step(60)
+    assert np.array_equal(s2.get_f(), f60)
+    s3 = _sel().from_case(c, "fp64")
+    s3.set_f(f30)
+    s3.step(30)
+    assert np.array_equal(s3.get_f(), f60)
+
+
+def test_nonfinite_detected():
+    sel = _sel()
+    c = CASES["tgv2d_ragged_N5"]
+    say("non-finite detection")
+    sim = sel.from_case(c, "fp64")
+    sim.step(2)
+    sim.sync()
+    f = sim.get_f()
+    f[3, 2, 7] = np.nan
+    sim.set_f(f)
+    with pytest.raises(sel.SelError) as ex:
+        sim.sync()
+    assert ex.value.code == sel.SEL_ENONFINITE
+    assert sim.reduce()[-1] >= 1
+
+
+def test_moments_device_matches_host():
+    c = CASES["tgv3d_q27_N4"]
+    say("moments device")
+    sim = _sel().from_case(c, "fp32dev")
+    sim.step(5)
+    d_rho = torch.empty((c.E, c.np_), dtype=torch.float64, device="cuda:0")
+    d_u = torch.empty((c.E, c.np_, 3), dtype=torch.float64, device="cuda:0")
+    sim.moments_device(d_rho, d_u)
+    torch.cuda.synchronize()
+    rho, u = sim.moments()
+    assert np.array_equal(d_rho.cpu().numpy(), rho)
+    assert np.array_equal(d_u.cpu().numpy(), u)
+
+
+def test_conservation_on_gpu():
+    """Mass and momentum to round-off over many filtered steps on a periodic
+    mesh (FP64): the drift stays at the level of one rounding per operation
+    and step (below 2e-15 of the total per step)."""
+    c = CASES["tgv3d_q27_N4"]
+    say("conservation")
+    sim = _sel().from_case(c, "fp64")
+    r0 = sim.reduce()
+    n = 300
+    sim.step(n)
+    r1 = sim.reduce()
+    assert abs(r1[0] - r0[0]) < 2e-15 * n * r0[0]
+    assert np.abs(r1[1:4] - r0[1:4]).max() < 2e-15 * n * r0[0]
