@@ -41,23 +41,37 @@ def src_hash() -> str:
 
 
 def algorithmic_bytes(info, Q, s):
-    """Bytes per launch and per step from the method's minimum traffic.
+    """Algorithmic bytes per step and per launch of each kernel kind.
 
-    Per step (all kernels): 8 state accesses per local node-velocity (SSPRK3:
+    Per step (the method): 8 state accesses per local node-velocity (SSPRK3:
     read f, write f1; read f, f1, write f2; read f, f2, write f) plus the
     metric and mass weight (dim^2 + 1 values per node) once per stage.
-    Later-stage element kernel (one launch): reads every unique operand value
-    once, reads the post-collision state and writes the result at element
-    interior nodes, writes the element contributions of element-boundary
-    nodes, and reads the metric, interior inverse mass and density."""
+    Per launch (what each kernel must move at least, every value once):
+      stage1   read the operand and write the post-collision state at every
+               unique node, write the density, write interior results and
+               the boundary-node element contributions, read the metric;
+      stage23  read the operand at every unique node, read the post-collision
+               state and write the result at interior nodes, write the
+               boundary-node contributions, read the metric, the interior
+               inverse mass and density;
+      assembly read the contributions, read two states and write one at every
+               node group, read the group mass and density and the member
+               lists (4-byte ints);
+      filter   read and write every unique node."""
     E, npn, dim = info["E"], info["np"], info["dim"]
     nb = info["boundary_nodes_per_element"]
     ni = npn - nb
     G = info["unique_nodes"]
+    ng = info["groups"]
     nv = E * npn * Q
     step = s * nv * (8 + 3 * (dim * dim + 1) / Q)
-    stage23 = s * (Q * G + 2 * Q * E * ni + Q * E * nb + E * npn * dim * dim + 2 * E * ni)
-    return nv, step, stage23
+    per = {
+        "stage1": s * (2 * Q * G + G + Q * E * ni + Q * E * nb + E * npn * dim * dim),
+        "stage23": s * (Q * G + 2 * Q * E * ni + Q * E * nb + E * npn * dim * dim + 2 * E * ni),
+        "assembly": s * (Q * E * nb + 3 * Q * ng + 2 * ng) + 4 * (E * nb + ng),
+        "filter": s * 2 * Q * G,
+    }
+    return nv, step, per
 
 
 def time_form(case, precision, steps, warmup, torch):
@@ -114,6 +128,8 @@ def main():
     ap.add_argument("--order", type=int, default=7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-other-form", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -128,6 +144,23 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate_copy:
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        dst.copy_(src)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "ms": ms,
+                          "GBs_read_plus_write": 2 * nbytes / (ms * 1e-3) / 1e9}), flush=True)
+        return
     sel.load()
     case = I.case_tgv3d(nel=args.nel, N=args.order, steps=0)
     forms = {}
@@ -141,25 +174,26 @@ def main():
     head = forms[args.precision]
     info = head["info"]
     s = 4 if args.precision == "fp32dev" else 8
-    nv, step_bytes, stage23_bytes = algorithmic_bytes(info, case.Q, s)
+    nv, step_bytes, per_kind = algorithmic_bytes(info, case.Q, s)
     value = nv / (head["ms_per_step"] * 1e-3) / 1e9
     kern = head["kernels"]
     dom = max(kern, key=lambda k: kern[k][0])
     dom_ms = kern[dom][0] / max(kern[dom][1], 1)
-    per_launch = {"stage23": stage23_bytes}.get(dom)
-    roof = None
-    if per_launch is not None:
-        ach = per_launch / (dom_ms * 1e-3) / 1e9
-        traffic = None
-        if os.path.exists(COUNTERS):
-            with open(COUNTERS) as fh:
-                cnt = json.load(fh)
-            if cnt.get("src_hash") == src_hash() and cnt.get("precision") == args.precision:
-                traffic = cnt.get("hbm_bytes_per_launch")
-        roof = {"bound": "hbm", "kernel": "k_stage (later SSPRK stages)", "achieved": round(ach, 1),
-                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4),
-                "traffic": traffic, "algorithmic_bytes_per_launch": int(per_launch),
-                "avg_launch_ms": round(dom_ms, 5)}
+    per_launch = per_kind[dom]
+    ach = per_launch / (dom_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(COUNTERS):
+        with open(COUNTERS) as fh:
+            cnt = json.load(fh)
+        if cnt.get("src_hash") == src_hash() and cnt.get("precision") == args.precision and \
+                cnt.get("kind", "stage23") == dom:
+            traffic = cnt.get("hbm_bytes_per_launch")
+    names = {"stage1": "k_stage first SSPRK stage", "stage23": "k_stage later SSPRK stages",
+             "assembly": "k_group shared-node assembly", "filter": "k_stage end-of-call filter"}
+    roof = {"bound": "hbm", "kernel": names[dom], "achieved": round(ach, 1),
+            "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4),
+            "traffic": traffic, "algorithmic_bytes_per_launch": int(per_launch),
+            "avg_launch_ms": round(dom_ms, 5)}
     step_gbs = step_bytes / (head["ms_per_step"] * 1e-3) / 1e9
     result = {
         "metric": METRIC,
@@ -183,7 +217,9 @@ def main():
         "step": {"algorithmic_bytes_per_step": int(step_bytes), "achieved": round(step_gbs, 1),
                  "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(step_gbs / PEAK_HBM_GBS, 4)},
         "kernels": {k: {"ms_total": round(v[0], 4), "launches": v[1],
-                        "avg_ms": round(v[0] / v[1], 5) if v[1] else None} for k, v in kern.items()},
+                        "avg_ms": round(v[0] / v[1], 5) if v[1] else None,
+                        "algorithmic_GBs": round(per_kind[k] / (v[0] / v[1] * 1e-3) / 1e9, 1) if v[1] else None}
+                    for k, v in kern.items()},
         "forms": {p: {"value": round(nv / (f["ms_per_step"] * 1e-3) / 1e9, 3),
                       "ms_per_step": round(f["ms_per_step"], 5)} for p, f in forms.items()},
         "src_hash": src_hash(),

@@ -92,7 +92,8 @@ typedef struct sel_params {
 
 /* Mesh ingest. Copies every array (the caller keeps ownership) and checks:
  * dim in {2,3}; supported N; E >= 1; gid in [0, E*np); nodes off the element
- * faces are not shared; face_tag in [0, ntags]; wall_u given when ntags > 0.
+ * faces are not shared; face_tag in [0, ntags]; 0 <= ntags <= 127; wall_u
+ * given when ntags > 0.
  * Element geometry (Jacobian > 0) is checked by sel_init on the device.
  * Returns SEL_EINVAL, SEL_EUNSUPPORTED or SEL_ENOMEM on failure. */
 int sel_mesh_create(int32_t dim, int32_t N, int64_t E, const double *xyz, const int64_t *gid,

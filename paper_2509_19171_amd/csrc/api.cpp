@@ -124,7 +124,8 @@ Plan make_plan(const sel_mesh *m, const sel_params *p)
     L.gmem = carve(c, 4 * (size_t)(E * m->nbe));
     L.ftag = carve(c, 4 * (size_t)(E * 2 * m->dim));
     L.wallu = carve(c, ts * 3 * (size_t)(m->ntags + 1));
-    for (int i = 0; i < 4; ++i) L.f[i] = carve(c, ts * (size_t)(p->Q * Gtot));
+    const int64_t nstate = (int64_t)p->Q * (E * m->nint + (m->ngrp + 63) / 64 * 64);
+    for (int i = 0; i < 4; ++i) L.f[i] = carve(c, ts * (size_t)nstate);
     L.rtb = carve(c, ts * (size_t)(p->Q * E * m->nbe));
     L.rhoc = carve(c, ts * (size_t)Gtot);
     L.io = carve(c, 8 * (size_t)(E * np * (m->dim + 1)));
@@ -241,6 +242,7 @@ extern "C" int sel_init(const sel_mesh *m, const sel_params *p, const double *rh
     s->ngrp = m->ngrp;
     s->Gi = m->E * (int64_t)m->nint;
     s->Gtot = s->Gi + m->ngrp;
+    s->nstate = (int64_t)p->Q * (s->Gi + (m->ngrp + 63) / 64 * 64);
     s->nwall = m->nwall;
     s->p = *p;
     s->prec = p->precision;
@@ -328,7 +330,7 @@ extern "C" int sel_init(const sel_mesh *m, const sel_params *p, const double *rh
 #undef UP
     if (hipMemsetAsync(s->flag, 0, 16, s->stream) != hipSuccess) return fail(SEL_EDEVICE);
     for (int i = 0; i < 4; ++i)
-        if (hipMemsetAsync(s->f[i], 0, s->tsize * p->Q * s->Gtot, s->stream) != hipSuccess) return fail(SEL_EDEVICE);
+        if (hipMemsetAsync(s->f[i], 0, s->tsize * s->nstate, s->stream) != hipSuccess) return fail(SEL_EDEVICE);
     if (hipMemsetAsync(s->rhoc, 0, s->tsize * s->Gtot, s->stream) != hipSuccess) return fail(SEL_EDEVICE);
     if ((rc = ops->geometry(s))) return fail(rc);
     if ((rc = ops->mass(s))) return fail(rc);

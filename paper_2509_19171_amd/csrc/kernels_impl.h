@@ -2,10 +2,11 @@
 // the order N, the lattice Q, the storage type T and the deviation form DEV.
 //
 // Data layout (all device, one workspace):
-//   state arrays [Q][Gtot]: velocity-major; for each velocity the element
-//     interiors come first (element e, interior slot s at e*NI + s), then the
-//     shared element-boundary nodes, one entry per node group (Gi + g).
-//   element contributions of boundary nodes rtb [Q][E*NB] (element-major).
+//   state arrays: element interiors [E][Q][NI] (node id e*NI + s), then the
+//     shared element-boundary nodes, one entry per node group, in tiles of 64
+//     groups [ceil(ngrp/64)][Q][64] (node id Gi + g). Every block touches a
+//     few contiguous regions; per velocity the accesses stay coalesced.
+//   element contributions of boundary nodes rtb [E][Q][NB].
 //   metric Gm [E][DIM*DIM][NP] = wJ dr_m/dx_k, interior 1/wJ [E][NI],
 //   assembled inverse mass of boundary groups [ngrp].
 // One workgroup handles EPB elements with one thread per node; a velocity
@@ -19,6 +20,12 @@
 namespace sel {
 
 constexpr double kCs2 = 1.0 / 3.0;
+
+// velocity planes staged in LDS per barrier in the element kernels
+#ifndef SEL_CHUNK
+#define SEL_CHUNK 3
+#endif
+
 
 __host__ __device__ constexpr int ipow_c(int b, int e) { return e == 0 ? 1 : b * ipow_c(b, e - 1); }
 
@@ -88,6 +95,21 @@ struct Geo {
     static constexpr int BLOCK = EPB * NP;
 };
 
+// State index of node id gix for velocity a is base + a * stride.
+constexpr int kTile = 64;
+struct SIdx {
+    int64_t base;
+    int stride;
+};
+__device__ __forceinline__ SIdx sidx_interior(int64_t e, int s, int Q, int NI)
+{
+    return {e * (int64_t)Q * NI + s, NI};
+}
+__device__ __forceinline__ SIdx sidx_group(int64_t g, int Q, int64_t QGi)
+{
+    return {QGi + (g / kTile) * (int64_t)Q * kTile + (g % kTile), kTile};
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs; hand each XCD a
 // contiguous range of element blocks so that neighbours share its L2.
 __device__ __forceinline__ int64_t xcd_block(int64_t nblk)
@@ -144,18 +166,18 @@ enum { M_STAGE1 = 0, M_STAGE23 = 1, M_LOCAL = 2, M_FILTER = 3 };
 
 template <typename T>
 struct StageArgs {
-    const T *op;     // operand state [Q][Gtot]
+    const T *op;     // operand state
     const T *f0in;   // post-collision state (stages 2, 3)
     T *f0out;        // stage 1: post-collision state written here
     T *rhoc;         // density at the collision [Gtot]
     T *out;          // output state (interior nodes; all owned nodes for M_FILTER)
-    T *rtb;          // element contributions of boundary nodes [Q][E*NB]
+    T *rtb;          // element contributions of boundary nodes [E][Q][NB]
     T *local;        // M_LOCAL: element contributions [Q][E][NP]
     const T *Gm, *invw, *D, *F;
     const int32_t *pcode, *bmap, *ftag;
     const uint8_t *bown;
     const T *wallu;  // [ntags+1][3]
-    int64_t E, nblk, Gi, Gtot;
+    int64_t E, nblk, Gi, QGi;
     T dt, omega, rho0, ca, cb, cc;  // output = ca f0 + cb f_k + cc L(f_k)
     T g[3];
     T fsc[kMaxQ];  // F* per unit density: t_a (e_a . g) / cs2
@@ -167,8 +189,15 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_stage(StageArgs<T> A)
 {
     using GG = Geo<DIM, N>;
     constexpr int n1 = GG::n1, NP = GG::NP, NI = GG::NI, NB = GG::NB, EPB = GG::EPB;
-    __shared__ T pl[3][EPB * NP];
-    __shared__ T sF[n1 * n1];
+    // first stage and filter keep all velocities of the node in registers
+    // (collision and filter need them); later stages stream the velocities
+    // with a software prefetch one chunk ahead. Velocities are processed in
+    // chunks of NA planes per LDS barrier.
+    constexpr bool ALLQ = (MODE == M_STAGE1 || MODE == M_FILTER);
+    constexpr int NA = SEL_CHUNK;
+    constexpr int NC = (Q + NA - 1) / NA;
+    __shared__ T pl[(ALLQ ? 3 : 2) * NA][EPB * NP];
+    __shared__ T sF[ALLQ ? n1 * n1 : 1];
 
     const int tid = threadIdx.x;
     const int le = tid / NP;
@@ -178,66 +207,119 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_stage(StageArgs<T> A)
     const int64_t e = eb * EPB + le;
     const bool valid = e < A.E;
     const bool filt = (MODE == M_FILTER) || (MODE == M_STAGE1 && A.filter);
-    if (filt) {
-        for (int q = tid; q < n1 * n1; q += GG::BLOCK) sF[q] = A.F[q];
+    if constexpr (ALLQ) {
+        if (filt)
+            for (int q = tid; q < n1 * n1; q += GG::BLOCK) sF[q] = A.F[q];
     }
     const int i = p % n1;
     const int j = (p / n1) % n1;
-    const int k = (DIM == 3) ? p / (n1 * n1) : 0;
+    int k = (DIM == 3) ? p / (n1 * n1) : 0;
+    // a k-slice of the N = 7 element is exactly one wavefront: k is uniform
+    if constexpr (DIM == 3 && n1 * n1 == 64 && EPB == 1) k = __builtin_amdgcn_readfirstlane(k);
     const int pc = A.pcode[p];
     const bool inner = pc >= 0;
     const int bsl = inner ? 0 : -pc - 1;
     int64_t gix = 0;
     bool own = false;
+    SIdx si{0, 0};
     if (valid) {
         if (inner) {
             gix = e * NI + pc;
             own = true;
+            si = sidx_interior(e, pc, Q, NI);
         } else {
-            gix = A.Gi + A.bmap[e * NB + bsl];
+            const int64_t g = A.bmap[e * NB + bsl];
+            gix = A.Gi + g;
             own = A.bown[e * NB + bsl] != 0;
+            si = sidx_group(g, Q, A.QGi);
         }
     }
     const int base = le * NP;
+    const int rowr = base + n1 * j + n1 * n1 * k;  // + c       (r line)
+    const int rows = base + i + n1 * n1 * k;       // + n1 c    (s line)
+    const int rowt = base + i + n1 * j;            // + n1^2 c  (t line)
 
-    // operand values of the node, all velocities
-    T fq[Q];
-    static_for<0, Q>([&](auto AA) {
-        constexpr int a = decltype(AA)::value;
-        fq[a] = valid ? A.op[(int64_t)a * A.Gtot + gix] : T(0);
-    });
-
-    if (filt) __syncthreads();  // sF visible
-    if (filt) {
-        // explicit modal filter (Sec. 2.2.3): (F x F x F) applied one direction at a time
+    T fq[ALLQ ? Q : 1];
+    // prefetch ring: even chunks in (roA, r0A), odd chunks in (roB, r0B)
+    T roA[NA] = {}, r0A[NA] = {}, roB[NA] = {}, r0B[NA] = {};
+    auto prefetch = [&](auto CC) {
+        constexpr int c = decltype(CC)::value;
+        if constexpr (!ALLQ && c < NC) {
+            static_for<0, NA>([&](auto UU) {
+                constexpr int u = decltype(UU)::value, a = c * NA + u;
+                if constexpr (a < Q) {
+                    const T vo = valid ? A.op[si.base + (int64_t)a * si.stride] : T(0);
+                    const T v0 = (MODE == M_STAGE23 && valid && inner) ? A.f0in[si.base + (int64_t)a * si.stride] : T(0);
+                    if constexpr (c & 1) {
+                        roB[u] = vo;
+                        r0B[u] = v0;
+                    } else {
+                        roA[u] = vo;
+                        r0A[u] = v0;
+                    }
+                }
+            });
+        }
+    };
+    if constexpr (ALLQ) {
         static_for<0, Q>([&](auto AA) {
             constexpr int a = decltype(AA)::value;
-            pl[0][base + p] = fq[a];
-            __syncthreads();
-            T t1 = 0;
-#pragma unroll
-            for (int c = 0; c < n1; ++c) t1 += sF[i * n1 + c] * pl[0][base + c + n1 * j + n1 * n1 * k];
-            pl[1][base + p] = t1;
-            __syncthreads();
-            T t2 = 0;
-#pragma unroll
-            for (int c = 0; c < n1; ++c) t2 += sF[j * n1 + c] * pl[1][base + i + n1 * c + n1 * n1 * k];
-            if constexpr (DIM == 3) {
-                pl[2][base + p] = t2;
-                __syncthreads();
-                T t3 = 0;
-#pragma unroll
-                for (int c = 0; c < n1; ++c) t3 += sF[k * n1 + c] * pl[2][base + i + n1 * j + n1 * n1 * c];
-                fq[a] = t3;
-            } else {
-                fq[a] = t2;
-            }
+            fq[a] = valid ? A.op[si.base + (int64_t)a * si.stride] : T(0);
         });
-        if (MODE == M_FILTER) {
+    } else {
+        prefetch(std::integral_constant<int, 0>{});
+    }
+
+    if constexpr (ALLQ) {
+        if (filt) {
+            __syncthreads();  // sF visible
+            // explicit modal filter (Sec. 2.2.3): (F x F x F) applied one direction at a time
+            static_for<0, NC>([&](auto CC) {
+                constexpr int c = decltype(CC)::value;
+                static_for<0, NA>([&](auto UU) {
+                    constexpr int u = decltype(UU)::value, a = c * NA + u;
+                    if constexpr (a < Q) pl[u][base + p] = fq[a];
+                });
+                __syncthreads();
+                static_for<0, NA>([&](auto UU) {
+                    constexpr int u = decltype(UU)::value, a = c * NA + u;
+                    if constexpr (a < Q) {
+                        T t1 = 0;
+#pragma unroll
+                        for (int q = 0; q < n1; ++q) t1 += sF[i * n1 + q] * pl[u][rowr + q];
+                        pl[NA + u][base + p] = t1;
+                    }
+                });
+                __syncthreads();
+                static_for<0, NA>([&](auto UU) {
+                    constexpr int u = decltype(UU)::value, a = c * NA + u;
+                    if constexpr (a < Q) {
+                        T t2 = 0;
+#pragma unroll
+                        for (int q = 0; q < n1; ++q) t2 += sF[j * n1 + q] * pl[NA + u][rows + n1 * q];
+                        if constexpr (DIM == 3) pl[2 * NA + u][base + p] = t2;
+                        else fq[a] = t2;
+                    }
+                });
+                if constexpr (DIM == 3) {
+                    __syncthreads();
+                    static_for<0, NA>([&](auto UU) {
+                        constexpr int u = decltype(UU)::value, a = c * NA + u;
+                        if constexpr (a < Q) {
+                            T t3 = 0;
+#pragma unroll
+                            for (int q = 0; q < n1; ++q) t3 += sF[k * n1 + q] * pl[2 * NA + u][rowt + n1 * n1 * q];
+                            fq[a] = t3;
+                        }
+                    });
+                }
+            });
+        }
+        if constexpr (MODE == M_FILTER) {
             if (valid && own) {
                 static_for<0, Q>([&](auto AA) {
                     constexpr int a = decltype(AA)::value;
-                    A.out[(int64_t)a * A.Gtot + gix] = fq[a];
+                    A.out[si.base + (int64_t)a * si.stride] = fq[a];
                 });
             }
             return;
@@ -245,18 +327,18 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_stage(StageArgs<T> A)
     }
 
     T rho = 0;
-    if (MODE == M_STAGE1) {
+    if constexpr (MODE == M_STAGE1) {
         if (valid) {
             collide_node<DIM, Q, T, DEV>(fq, A.rho0, A.omega, A.dt, A.g, rho);
             if (own) {
                 static_for<0, Q>([&](auto AA) {
                     constexpr int a = decltype(AA)::value;
-                    A.f0out[(int64_t)a * A.Gtot + gix] = fq[a];
+                    A.f0out[si.base + (int64_t)a * si.stride] = fq[a];
                 });
                 A.rhoc[gix] = rho;
             }
         }
-    } else if (MODE == M_STAGE23) {
+    } else if constexpr (MODE == M_STAGE23) {
         if (valid && inner) rho = A.rhoc[gix];
     }
 
@@ -274,92 +356,116 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_stage(StageArgs<T> A)
 #pragma unroll
         for (int q = 0; q < DIM; ++q) Gr[m][q] = valid ? A.Gm[(e * DIM * DIM + m * DIM + q) * NP + p] : T(0);
     T invw = 0;
-    if (valid && inner && MODE != M_LOCAL) invw = A.invw[e * NI + pc];
+    if (MODE != M_LOCAL && valid && inner) invw = A.invw[e * NI + pc];
 
-    // wall faces through this node (flux bounce-back, Sec. 2.2.1): outward
-    // area vector w_s J_s n = +-(w_end)^-1 wJ dr_m/dx on face r_m = +-1
-    int nw = 0;
-    T wA[DIM][3];
-    T wub[DIM][3];
+    // wall faces through this node (flux bounce-back, Sec. 2.2.1): at most
+    // one per reference direction m; 8 bits per direction hold the wall tag
+    // (0 = none) and bit 7 the side (plus face r_m = +1)
+    uint32_t wcode = 0;
     if (valid && !inner) {
-        const int idx[3] = {i, j, k};
 #pragma unroll
         for (int m = 0; m < DIM; ++m) {
-            if (idx[m] == 0 || idx[m] == N) {
-                const int fc = 2 * m + (idx[m] == N ? 1 : 0);
-                const int tag = A.ftag[e * 2 * DIM + fc];
-                if (tag > 0) {
-                    const T sc = (idx[m] == N ? T(1) : T(-1)) * T(N * (N + 1)) / T(2);
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) {
-                        wA[nw][q] = (q < DIM) ? sc * Gr[m][q] : T(0);
-                        wub[nw][q] = A.wallu[tag * 3 + q];
-                    }
-                    ++nw;
-                }
+            const int idx = (m == 0) ? i : (m == 1) ? j : k;
+            if (idx == 0 || idx == N) {
+                const int fc = 2 * m + (idx == N ? 1 : 0);
+                const uint32_t tag = (uint32_t)A.ftag[e * 2 * DIM + fc];
+                if (tag > 0) wcode |= (tag | (idx == N ? 0x80u : 0u)) << (8 * m);
             }
         }
     }
 
     // streaming operator per velocity (Sec. 2.2): rt = -wJ e . grad f (+ wall flux)
-    static_for<0, Q>([&](auto AA) {
-        constexpr int a = decltype(AA)::value;
-        constexpr int ex = lat_e<DIM, Q>(a, 0), ey = lat_e<DIM, Q>(a, 1), ez = lat_e<DIM, Q>(a, 2);
-        T *P = pl[a & 1];
-        P[base + p] = fq[a];
+    static_for<0, NC>([&](auto CC) {
+        constexpr int c = decltype(CC)::value;
+        prefetch(std::integral_constant<int, c + 1>{});
+        constexpr int pb = (c & 1) * NA;  // double-buffered plane set
+        static_for<0, NA>([&](auto UU) {
+            constexpr int u = decltype(UU)::value, a = c * NA + u;
+            if constexpr (a < Q) {
+                if constexpr (ALLQ) pl[pb + u][base + p] = fq[a];
+                else if constexpr (c & 1) pl[pb + u][base + p] = roB[u];
+                else pl[pb + u][base + p] = roA[u];
+            }
+        });
         __syncthreads();
-        T dr = 0, ds = 0, dtt = 0;
+        static_for<0, NA>([&](auto UU) {
+            constexpr int u = decltype(UU)::value, a = c * NA + u;
+            if constexpr (a < Q) {
+                constexpr int ex = lat_e<DIM, Q>(a, 0), ey = lat_e<DIM, Q>(a, 1), ez = lat_e<DIM, Q>(a, 2);
+                const T *P = pl[pb + u];
+                T v;
+                if constexpr (ALLQ) v = fq[a];
+                else if constexpr (c & 1) v = roB[u];
+                else v = roA[u];
+                T dr = 0, ds = 0, dtt = 0;
 #pragma unroll
-        for (int c = 0; c < n1; ++c) dr += Di[c] * P[base + c + n1 * j + n1 * n1 * k];
+                for (int q = 0; q < n1; ++q) dr += Di[q] * P[rowr + q];
 #pragma unroll
-        for (int c = 0; c < n1; ++c) ds += Dj[c] * P[base + i + n1 * c + n1 * n1 * k];
-        if constexpr (DIM == 3) {
+                for (int q = 0; q < n1; ++q) ds += Dj[q] * P[rows + n1 * q];
+                if constexpr (DIM == 3) {
 #pragma unroll
-            for (int c = 0; c < n1; ++c) dtt += Dk[c] * P[base + i + n1 * j + n1 * n1 * c];
-        }
-        // c_m = sum_k e_k G_mk
-        T cr = 0, cs = 0, ct = 0;
-        if constexpr (ex != 0) {
-            cr += T(ex) * Gr[0][0];
-            cs += T(ex) * Gr[1][0];
-            if constexpr (DIM == 3) ct += T(ex) * Gr[2][0];
-        }
-        if constexpr (ey != 0) {
-            cr += T(ey) * Gr[0][1];
-            cs += T(ey) * Gr[1][1];
-            if constexpr (DIM == 3) ct += T(ey) * Gr[2][1];
-        }
-        if constexpr (DIM == 3 && ez != 0) {
-            cr += T(ez) * Gr[0][2];
-            cs += T(ez) * Gr[1][2];
-            ct += T(ez) * Gr[2][2];
-        }
-        T rt = -(cr * dr + cs * ds + ct * dtt);
-        if (nw > 0) {
-            constexpr int b = lat_opp<DIM, Q>(a);
-            const T t = T(lat_t<DIM, Q>(a));
+                    for (int q = 0; q < n1; ++q) dtt += Dk[q] * P[rowt + n1 * n1 * q];
+                }
+                // c_m = sum_k e_k G_mk
+                T cr = 0, cs = 0, ct = 0;
+                if constexpr (ex != 0) {
+                    cr += T(ex) * Gr[0][0];
+                    cs += T(ex) * Gr[1][0];
+                    if constexpr (DIM == 3) ct += T(ex) * Gr[2][0];
+                }
+                if constexpr (ey != 0) {
+                    cr += T(ey) * Gr[0][1];
+                    cs += T(ey) * Gr[1][1];
+                    if constexpr (DIM == 3) ct += T(ey) * Gr[2][1];
+                }
+                if constexpr (DIM == 3 && ez != 0) {
+                    cr += T(ez) * Gr[0][2];
+                    cs += T(ez) * Gr[1][2];
+                    ct += T(ez) * Gr[2][2];
+                }
+                T rt = -(cr * dr + cs * ds + ct * dtt);
+                if (wcode) {
+                    // outward area vector w_s J_s n = +-(w_end)^-1 wJ dr_m/dx on the
+                    // face r_m = +-1, from the same metric as the volume term
+                    constexpr int b = lat_opp<DIM, Q>(a);
+                    const T t = T(lat_t<DIM, Q>(a));
+                    T vb;
+                    if constexpr (ALLQ) vb = fq[b];
+                    else vb = A.op[si.base + (int64_t)b * si.stride];
 #pragma unroll
-            for (int w = 0; w < DIM; ++w) {
-                if (w < nw) {
-                    const T ne = T(ex) * wA[w][0] + T(ey) * wA[w][1] + T(ez) * wA[w][2];
-                    if (ne < T(0)) {
-                        const T eub = T(ex) * wub[w][0] + T(ey) * wub[w][1] + T(ez) * wub[w][2];
-                        rt += ne * (fq[a] - fq[b] - T(2) * t * A.rho0 * eub * T(3));
+                    for (int m = 0; m < DIM; ++m) {
+                        const uint32_t code = (wcode >> (8 * m)) & 0xffu;
+                        if (code) {
+                            const T sc = ((code & 0x80u) ? T(1) : T(-1)) * T(N * (N + 1)) / T(2);
+                            T ne = T(ex) * Gr[m][0] + T(ey) * Gr[m][1];
+                            if constexpr (DIM == 3) ne += T(ez) * Gr[m][2];
+                            ne *= sc;
+                            if (ne < T(0)) {
+                                const T *ub = A.wallu + 3 * (code & 0x7fu);
+                                const T eub = T(ex) * ub[0] + T(ey) * ub[1] + T(ez) * ub[2];
+                                rt += ne * (v - vb - T(2) * t * A.rho0 * eub * T(3));
+                            }
+                        }
+                    }
+                }
+                if (valid) {
+                    if constexpr (MODE == M_LOCAL) {
+                        A.local[((int64_t)a * A.E + e) * NP + p] = rt;
+                    } else {
+                        if (inner) {
+                            const T L = rt * invw + A.fsc[a] * rho;
+                            T f0v;
+                            if constexpr (MODE == M_STAGE1) f0v = v;
+                            else if constexpr (c & 1) f0v = r0B[u];
+                            else f0v = r0A[u];
+                            A.out[si.base + (int64_t)a * si.stride] = A.ca * f0v + A.cb * v + A.cc * L;
+                        } else {
+                            A.rtb[(e * Q + a) * NB + bsl] = rt;
+                        }
                     }
                 }
             }
-        }
-        if (valid) {
-            if (MODE == M_LOCAL) {
-                A.local[((int64_t)a * A.E + e) * NP + p] = rt;
-            } else if (inner) {
-                const T L = rt * invw + A.fsc[a] * rho;
-                const T f0v = (MODE == M_STAGE1) ? fq[a] : A.f0in[(int64_t)a * A.Gtot + gix];
-                A.out[(int64_t)a * A.Gtot + gix] = A.ca * f0v + A.cb * fq[a] + A.cc * L;
-            } else {
-                A.rtb[(int64_t)a * (A.E * NB) + e * NB + bsl] = rt;
-            }
-        }
+        });
     });
 }
 
@@ -367,30 +473,50 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_stage(StageArgs<T> A)
 // Direct stiffness summation at shared nodes (continuous Galerkin): the
 // element contributions of a node group are summed in ascending member order,
 // scaled by the assembled inverse mass, F* is added and the Runge-Kutta
-// combination written once for the group.
+// combination written once for the group. One thread per group, all
+// velocities; the member list is read once.
 template <typename T>
 struct GroupArgs {
     const T *rtb, *f0, *fk, *rhoc, *invMb;
     T *out;
     const int32_t *goff, *gmem;
-    int64_t ngrp, Gi, Gtot, EB;
+    int64_t ngrp, Gi, QGi;
+    int NB;
     T ca, cb, cc;
     T fsc[kMaxQ];
 };
 
-template <typename T>
+template <int Q, typename T>
 __global__ void __launch_bounds__(256) k_group(GroupArgs<T> A)
 {
+    constexpr int MM = 8;  // member offsets kept in registers (more are re-read)
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int a = blockIdx.y;
     if (g >= A.ngrp) return;
-    const int j0 = A.goff[g], j1 = A.goff[g + 1];
-    const T *r = A.rtb + (int64_t)a * A.EB;
-    T s = 0;
-    for (int q = j0; q < j1; ++q) s += r[A.gmem[q]];
-    const int64_t ix = (int64_t)a * A.Gtot + A.Gi + g;
-    const T L = s * A.invMb[g] + A.fsc[a] * A.rhoc[A.Gi + g];
-    A.out[ix] = A.ca * A.f0[ix] + A.cb * A.fk[ix] + A.cc * L;
+    const int j0 = A.goff[g];
+    const int nm = A.goff[g + 1] - j0;
+    // member lb = e NB + b holds its velocity a at (e Q + a) NB + b
+    auto moff = [&](int64_t lb) {
+        const int64_t e = lb / A.NB;
+        return e * (int64_t)Q * A.NB + (lb - e * A.NB);
+    };
+    int64_t mm[MM];
+#pragma unroll
+    for (int t = 0; t < MM; ++t) mm[t] = moff(A.gmem[j0 + (t < nm ? t : 0)]);
+    const T invM = A.invMb[g];
+    const T rho = A.rhoc[A.Gi + g];
+    const SIdx si = sidx_group(g, Q, A.QGi);
+    static_for<0, Q>([&](auto AA) {
+        constexpr int a = decltype(AA)::value;
+        const T *r = A.rtb + (int64_t)a * A.NB;
+        T s = 0;
+#pragma unroll
+        for (int t = 0; t < MM; ++t)
+            if (t < nm) s += r[mm[t]];
+        for (int t = MM; t < nm; ++t) s += r[moff(A.gmem[j0 + t])];
+        const int64_t ix = si.base + (int64_t)a * si.stride;
+        const T L = s * invM + A.fsc[a] * rho;
+        A.out[ix] = A.ca * A.f0[ix] + A.cb * A.fk[ix] + A.cc * L;
+    });
 }
 
 // ---------------------------------------------------------------- geometry --
@@ -485,24 +611,25 @@ __global__ void k_mass_grp(const double *wJ, const int32_t *bpos, const int32_t 
 struct NodeMap {
     const int32_t *pcode, *bmap;
     const uint8_t *bown;
-    int64_t E, Gi;
-    int NP, NI, NB;
-    __device__ __forceinline__ int64_t gix(int64_t e, int p, bool &own) const
+    int64_t E, Gi, QGi;
+    int NP, NI, NB, Q;
+    // state index of element node (e, p); own = this copy writes shared nodes
+    __device__ __forceinline__ SIdx sidx(int64_t e, int p, bool &own) const
     {
         const int pc = pcode[p];
         if (pc >= 0) {
             own = true;
-            return e * NI + pc;
+            return sidx_interior(e, pc, Q, NI);
         }
         const int b = -pc - 1;
         own = bown[e * NB + b] != 0;
-        return Gi + bmap[e * NB + b];
+        return sidx_group(bmap[e * NB + b], Q, QGi);
     }
 };
 
 // f-bar = f^eq(rho, u) - dt F** / 2 (Sec. 2.1 with f = f^eq), computed in FP64
 template <int DIM, int Q, typename T, bool DEV>
-__global__ void k_init(NodeMap M, const double *rho, const double *u, T *f, int64_t Gtot, double rho0, double dt,
+__global__ void k_init(NodeMap M, const double *rho, const double *u, T *f, double rho0, double dt,
                        double g0, double g1, double g2)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -510,7 +637,7 @@ __global__ void k_init(NodeMap M, const double *rho, const double *u, T *f, int6
     const int64_t e = q / M.NP;
     const int p = (int)(q - e * M.NP);
     bool own;
-    const int64_t gi = M.gix(e, p, own);
+    const SIdx si = M.sidx(e, p, own);
     if (!own) return;
     const double r = rho[q];
     double uu[3] = {0, 0, 0};
@@ -528,48 +655,48 @@ __global__ void k_init(NodeMap M, const double *rho, const double *u, T *f, int6
         const double fss = t * (9.0 * eu * eF - 3.0 * uF);
         double v = feq - 0.5 * dt * fss;
         if (DEV) v -= t * rho0;
-        f[(int64_t)a * Gtot + gi] = T(v);
+        f[si.base + (int64_t)a * si.stride] = T(v);
     });
 }
 
 // one velocity plane between the state and an FP64 element-node array
 template <typename T>
-__global__ void k_scatter_plane(NodeMap M, const double *src, T *dst, int64_t Gtot, int a, double off)
+__global__ void k_scatter_plane(NodeMap M, const double *src, T *dst, int a, double off)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= M.E * M.NP) return;
     const int64_t e = q / M.NP;
     const int p = (int)(q - e * M.NP);
     bool own;
-    const int64_t gi = M.gix(e, p, own);
-    if (own) dst[(int64_t)a * Gtot + gi] = T(src[q] - off);
+    const SIdx si = M.sidx(e, p, own);
+    if (own) dst[si.base + (int64_t)a * si.stride] = T(src[q] - off);
 }
 template <typename T>
-__global__ void k_gather_plane(NodeMap M, const T *src, double *dst, int64_t Gtot, int a, double off)
+__global__ void k_gather_plane(NodeMap M, const T *src, double *dst, int a, double off)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= M.E * M.NP) return;
     const int64_t e = q / M.NP;
     const int p = (int)(q - e * M.NP);
     bool own;
-    const int64_t gi = M.gix(e, p, own);
-    dst[q] = double(src[(int64_t)a * Gtot + gi]) + off;
+    const SIdx si = M.sidx(e, p, own);
+    dst[q] = double(src[si.base + (int64_t)a * si.stride]) + off;
 }
 
 // moments (Eqs. pressure, momentum) in FP64 at every element node
 template <int DIM, int Q, typename T, bool DEV>
-__global__ void k_moments(NodeMap M, const T *f, int64_t Gtot, double rho0, double *rho, double *u)
+__global__ void k_moments(NodeMap M, const T *f, double rho0, double *rho, double *u)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= M.E * M.NP) return;
     const int64_t e = q / M.NP;
     const int p = (int)(q - e * M.NP);
     bool own;
-    const int64_t gi = M.gix(e, p, own);
+    const SIdx si = M.sidx(e, p, own);
     double m = 0, j[3] = {0, 0, 0};
     static_for<0, Q>([&](auto AA) {
         constexpr int a = decltype(AA)::value;
-        const double v = double(f[(int64_t)a * Gtot + gi]);
+        const double v = double(f[si.base + (int64_t)a * si.stride]);
         m += v;
         if constexpr (lat_e<DIM, Q>(a, 0) != 0) j[0] += lat_e<DIM, Q>(a, 0) * v;
         if constexpr (lat_e<DIM, Q>(a, 1) != 0) j[1] += lat_e<DIM, Q>(a, 1) * v;
@@ -583,7 +710,7 @@ __global__ void k_moments(NodeMap M, const T *f, int64_t Gtot, double rho0, doub
 // FP64 integrals with the lumped mass and a non-finite count; per-block
 // partial sums in fixed order, summed by k_reduce_final.
 template <int DIM, int Q, typename T, bool DEV>
-__global__ void __launch_bounds__(256) k_reduce(NodeMap M, const T *f, int64_t Gtot, int Q_, const double *wJ,
+__global__ void __launch_bounds__(256) k_reduce(NodeMap M, const T *f, int64_t nstate, const double *wJ,
                                                 double rho0, double *part)
 {
     __shared__ double sh[8][256];
@@ -593,11 +720,11 @@ __global__ void __launch_bounds__(256) k_reduce(NodeMap M, const T *f, int64_t G
         const int64_t e = q / M.NP;
         const int p = (int)(q - e * M.NP);
         bool own;
-        const int64_t gi = M.gix(e, p, own);
+        const SIdx si = M.sidx(e, p, own);
         double m = 0, j[3] = {0, 0, 0};
         static_for<0, Q>([&](auto AA) {
             constexpr int a = decltype(AA)::value;
-            const double v = double(f[(int64_t)a * Gtot + gi]);
+            const double v = double(f[si.base + (int64_t)a * si.stride]);
             m += v;
             if constexpr (lat_e<DIM, Q>(a, 0) != 0) j[0] += lat_e<DIM, Q>(a, 0) * v;
             if constexpr (lat_e<DIM, Q>(a, 1) != 0) j[1] += lat_e<DIM, Q>(a, 1) * v;
@@ -613,8 +740,7 @@ __global__ void __launch_bounds__(256) k_reduce(NodeMap M, const T *f, int64_t G
         }
         acc[4] += wj * 0.5 * rho0 * u2;
     }
-    const int64_t nv = (int64_t)Q_ * Gtot;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nv; q += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nstate; q += (int64_t)gridDim.x * blockDim.x) {
         const T v = f[q];
         if (!(v == v) || v - v != T(0)) acc[5] += 1.0;
     }

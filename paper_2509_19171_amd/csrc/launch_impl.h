@@ -31,9 +31,11 @@ struct Impl {
         M.bown = s->bown;
         M.E = s->E;
         M.Gi = s->Gi;
+        M.QGi = (int64_t)Q * s->Gi;
         M.NP = NP;
         M.NI = NI;
         M.NB = NB;
+        M.Q = Q;
         return M;
     }
 
@@ -52,7 +54,7 @@ struct Impl {
         A.E = s->E;
         A.nblk = nblk(s);
         A.Gi = s->Gi;
-        A.Gtot = s->Gtot;
+        A.QGi = (int64_t)Q * s->Gi;
         A.dt = T(s->p.dt);
         A.omega = T(s->omega);
         A.rho0 = T(s->p.rho0);
@@ -73,8 +75,8 @@ struct Impl {
         B.gmem = s->gmem;
         B.ngrp = s->ngrp;
         B.Gi = s->Gi;
-        B.Gtot = s->Gtot;
-        B.EB = s->E * NB;
+        B.QGi = (int64_t)Q * s->Gi;
+        B.NB = NB;
         for (int a = 0; a < Q; ++a) B.fsc[a] = T(s->fsc[a]);
         return B;
     }
@@ -110,10 +112,10 @@ struct Impl {
     static int launch_group(sel_sim *s, const GroupArgs<T> &B)
     {
         if (s->ngrp == 0) return SEL_OK;
-        dim3 grid((unsigned)((s->ngrp + 255) / 256), Q), block(256);
+        dim3 grid((unsigned)((s->ngrp + 255) / 256)), block(256);
         hipEvent_t ev = nullptr;
         if (int rc = tic(s, 2, ev)) return rc;
-        hipLaunchKernelGGL((k_group<T>), grid, block, 0, s->stream, B);
+        hipLaunchKernelGGL((k_group<Q, T>), grid, block, 0, s->stream, B);
         SEL_LAUNCH_CHECK();
         return toc(s, ev);
     }
@@ -145,7 +147,7 @@ struct Impl {
     {
         const int64_t nl = s->E * NP;
         hipLaunchKernelGGL((k_init<DIM, Q, T, DEV>), dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, s->stream,
-                           nodemap(s), d_rho, d_u, st(s, s->cur), s->Gtot, s->p.rho0, s->p.dt, s->p.accel[0],
+                           nodemap(s), d_rho, d_u, st(s, s->cur), s->p.rho0, s->p.dt, s->p.accel[0],
                            s->p.accel[1], DIM == 3 ? s->p.accel[2] : 0.0);
         SEL_LAUNCH_CHECK();
         return SEL_OK;
@@ -225,7 +227,7 @@ struct Impl {
     {
         const int64_t nl = s->E * NP;
         hipLaunchKernelGGL((k_moments<DIM, Q, T, DEV>), dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, s->stream,
-                           nodemap(s), st(s, s->cur), s->Gtot, s->p.rho0, d_rho, d_u);
+                           nodemap(s), st(s, s->cur), s->p.rho0, d_rho, d_u);
         SEL_LAUNCH_CHECK();
         return SEL_OK;
     }
@@ -233,7 +235,7 @@ struct Impl {
     static int reduce(sel_sim *s)
     {
         hipLaunchKernelGGL((k_reduce<DIM, Q, T, DEV>), dim3(s->nred), dim3(256), 0, s->stream, nodemap(s),
-                           st(s, s->cur), s->Gtot, Q, s->wJ, s->p.rho0, s->red);
+                           st(s, s->cur), s->nstate, s->wJ, s->p.rho0, s->red);
         SEL_LAUNCH_CHECK();
         hipLaunchKernelGGL((k_reduce_final<T>), dim3(1), dim3(64), 0, s->stream, s->red, s->nred, s->red + 8 * s->nred);
         SEL_LAUNCH_CHECK();
@@ -244,7 +246,7 @@ struct Impl {
     {
         const int64_t nl = s->E * NP;
         hipLaunchKernelGGL((k_scatter_plane<T>), dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, s->stream,
-                           nodemap(s), d_plane, static_cast<T *>(dst), s->Gtot, a, sub ? s->toff[a] : 0.0);
+                           nodemap(s), d_plane, static_cast<T *>(dst), a, sub ? s->toff[a] : 0.0);
         SEL_LAUNCH_CHECK();
         return SEL_OK;
     }
@@ -253,7 +255,7 @@ struct Impl {
     {
         const int64_t nl = s->E * NP;
         hipLaunchKernelGGL((k_gather_plane<T>), dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, s->stream,
-                           nodemap(s), static_cast<const T *>(src), d_plane, s->Gtot, a, add ? s->toff[a] : 0.0);
+                           nodemap(s), static_cast<const T *>(src), d_plane, a, add ? s->toff[a] : 0.0);
         SEL_LAUNCH_CHECK();
         return SEL_OK;
     }

@@ -39,6 +39,10 @@ extern "C" int sel_mesh_create(int32_t dim, int32_t N, int64_t E, const double *
         set_error("sel_mesh_create: ntags < 0 or wall_u missing");
         return SEL_EINVAL;
     }
+    if (ntags > 127) {
+        set_error("sel_mesh_create: at most 127 wall tags");
+        return SEL_EUNSUPPORTED;
+    }
     sel_mesh *m = new (std::nothrow) sel_mesh();
     if (!m) {
         set_error("sel_mesh_create: out of host memory");
@@ -78,21 +82,32 @@ extern "C" int sel_mesh_create(int32_t dim, int32_t N, int64_t E, const double *
         m->nwall = 0;
         for (int32_t v : m->ftag) m->nwall += (v > 0);
 
-        // structural classes: interior nodes (no index at 0 or N) and boundary slots
+        // structural classes: interior nodes (no index at 0 or N) and boundary
+        // slots. Boundary slots are numbered face by face (face interiors in
+        // face order, then edges, then corners), so that the nodes of one
+        // shared face are a contiguous slot range in both elements.
         m->pcode.resize(m->np);
         m->bpos.resize(m->nbe);
-        int ns = 0, nb = 0;
+        std::vector<std::pair<int64_t, int>> bkey;
+        int ns = 0;
         for (int p = 0; p < m->np; ++p) {
             int ijk[3] = {p % m->n1, (p / m->n1) % m->n1, dim == 3 ? p / (m->n1 * m->n1) : 1};
-            bool inner = true;
-            for (int d = 0; d < dim; ++d) inner = inner && ijk[d] > 0 && ijk[d] < N;
-            if (inner) {
+            int nbd = 0, cls = 0;
+            for (int d = 0; d < dim; ++d)
+                if (ijk[d] == 0 || ijk[d] == N) {
+                    ++nbd;
+                    cls = cls * 8 + 2 * d + (ijk[d] == N ? 1 : 0) + 1;
+                }
+            if (nbd == 0) {
                 m->pcode[p] = ns++;
             } else {
-                m->bpos[nb] = p;
-                m->pcode[p] = -(nb + 1);
-                ++nb;
+                bkey.push_back({((int64_t)nbd << 40) | ((int64_t)cls << 20) | p, p});
             }
+        }
+        std::sort(bkey.begin(), bkey.end());
+        for (int b = 0; b < (int)bkey.size(); ++b) {
+            m->bpos[b] = bkey[b].second;
+            m->pcode[bkey[b].second] = -(b + 1);
         }
 
         // global ids: range check and no sharing of interior nodes

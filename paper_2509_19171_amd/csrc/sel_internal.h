@@ -64,6 +64,7 @@ struct sel_sim {
     // copy of mesh scalars
     int dim = 0, N = 0, n1 = 0, np = 0, nint = 0, nbe = 0, Q = 0;
     int64_t E = 0, ngrp = 0, Gi = 0, Gtot = 0, nwall = 0;
+    int64_t nstate = 0;        // entries of one state array (Q per node, groups padded to tiles of 64)
     sel_params p{};
     int prec = SEL_FP64;
     size_t tsize = 8;
@@ -92,8 +93,8 @@ struct sel_sim {
     int32_t *gmem = nullptr;   // [E*nbe]
     int32_t *ftag = nullptr;   // [E][2 dim]
     void *wallu = nullptr;     // T [ntags+1][3], row 0 = zero
-    void *f[4] = {};           // T [Q][Gtot]: state, f0, stage a, stage b
-    void *rtb = nullptr;       // T [Q][E*nbe]
+    void *f[4] = {};           // T [nstate]: state, f0, stage a, stage b
+    void *rtb = nullptr;       // T [E][Q][nbe]
     void *rhoc = nullptr;      // T [Gtot]
     double *io = nullptr;      // FP64 [E][np][dim+1] (moments / per-velocity transfers)
     double *red = nullptr;     // FP64 [nred][8] partial sums

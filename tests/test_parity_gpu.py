@@ -3,9 +3,10 @@ oracle on the same seeded inputs.
 
 Tolerances (normwise relative error max|a - b| / max|b|):
   FP64 storage: 1e-12 on f, rho, u and the geometry (single operators and
-  whole runs); velocities are normalised by max(max|u|, 0.01 c_s), since a
-  flow started from rest carries the absolute round-off of the O(1)
-  distribution (summation order differs between the two sides);
+  whole runs); velocities are normalised by max(max|u|, 0.01 c) with c = 1
+  the lattice speed, since u is formed from differences of O(1) populations
+  and a flow started from rest carries their absolute round-off (summation
+  order differs between the two sides);
   FP32 deviation storage: 1e-5 on rho and u after 200 steps, 2e-6 on
   single operators (FP32 rounding of O(1) quantities, eps_32 = 6e-8, times
   the conditioning of the collocation derivative, ~N^2).
@@ -28,8 +29,8 @@ CS = 3 ** -0.5
 
 
 def uerr(u, uref):
-    """Velocity error normalised by max(max|u_ref|, 0.01 c_s)."""
-    return float(np.abs(u - uref).max() / max(np.abs(uref).max(), 0.01 * CS))
+    """Velocity error normalised by max(max|u_ref|, 0.01 c), c = 1."""
+    return float(np.abs(u - uref).max() / max(np.abs(uref).max(), 0.01))
 
 
 def say(msg):
