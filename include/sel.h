@@ -72,7 +72,10 @@ typedef struct sel_sim sel_sim;
  *   accel: body acceleration g, force density F = rho g (Sec. 2.1, Eqs. body
  *   and f_c; Sec. 3.5 drives the pipe with (0, 0, rho g)).
  *   closure / closure_len: host pointer to the FP32 parameter blob of the
- *   learned relaxation-time closure (layout in sel_closure_layout) or NULL. */
+ *   learned relaxation-time closure (layout below, closure_len must equal
+ *   sel_closure_len()) or NULL. With a blob, every step first evaluates the
+ *   closure on the current state and relaxes each node with
+ *   omega = 1 / (tau + dtau + 1/2). */
 typedef struct sel_params {
     int32_t Q;           /* 9 (dim 2), 19 or 27 (dim 3) */
     int32_t precision;   /* SEL_FP64 or SEL_FP32_DEV */
@@ -174,6 +177,86 @@ int sel_geometry(sel_sim *sim, double *wJ, double *J);
 void *sel_stream(const sel_sim *sim);
 
 int sel_destroy(sel_sim *sim);
+
+/* ---- learned relaxation-time closure ----------------------------------
+ * Not part of the paper's method (it has none): a per-node MLP that maps
+ * local invariants of the state to an increment dtau >= 0 of the BGK
+ * relaxation time (Sec. 2.1) for under-resolved runs.
+ *
+ * Features per node (FP32), from f-bar of Sec. 2.1 with u = sum e f / rho,
+ * A = grad u from the element-local derivative (Sec. 2.2), S and W its
+ * symmetric and antisymmetric parts, Pi = sum_a e e (f_a - f_a^eq),
+ * lam = nu / c_s^2:
+ *   x = [lam^2 S:S, lam^2 W:W, lam^3 tr(S^3), lam^3 tr(S W W),
+ *        Pi:Pi / (rho c_s^2)^2, lam Pi:S / (rho c_s^2)].
+ * Network: x' = (x - mean) / std, h1 = tanh(W1 x' + b1), h2 = tanh(W2 h1 + b2),
+ * h3 = tanh(W3 h2 + b3), z = w4 . h3 + b4 (6 -> 64 -> 64 -> 64 -> 1),
+ * dtau = tau softplus(z); a non-finite value, a negative one or one above
+ * dtau_max * tau is replaced by 0 (the plain method).
+ * Blob (FP32, this order): mean[6], std[6], W1[64][6], b1[64], W2[64][64],
+ * b2[64], W3[64][64], b3[64], w4[64], b4, dtau_max. The trainable
+ * parameters are the contiguous range W1 .. b4 (8833 values) starting at
+ * float offset 12. */
+
+/* Number of floats in the blob (8846). */
+int64_t sel_closure_len(void);
+
+/* Replace the blob of a simulation created with one (host pointer, len =
+ * sel_closure_len()); NULL switches the closure off (plain method) until the
+ * next call with a blob. Synchronises. SEL_ESTATE if the simulation was
+ * created without a blob. */
+int sel_closure_set(sel_sim *sim, const float *params, int64_t len);
+
+/* Features of the current state, d_X [E][np][6] FP32 device array (every
+ * element copy of a node), enqueued on the stream. */
+int sel_closure_features(sel_sim *sim, float *d_X);
+
+/* Increments the next step would use, d_dtau [number of unique nodes] FP32
+ * device array in the library's node-id order (diagnostics). */
+int sel_closure_dtau(sel_sim *sim, float *d_dtau);
+
+/* Coarse graining of a fine simulation onto a coarse one over the same
+ * elements (same dim, lattice, storage, E; coarse N <= fine N): each
+ * distribution is projected element by element onto the modes k <= N_c of the
+ * basis phi_0 = L_0, phi_1 = L_1, phi_k = L_k - L_{k-2} (the filter basis of
+ * Sec. 2.2.3) and evaluated at the coarse GLL nodes; shared coarse nodes take
+ * the lowest-numbered element's value. Overwrites the coarse state (time and
+ * step count unchanged). Synchronises both streams. */
+int sel_coarse_grain(const sel_sim *fine, sel_sim *coarse);
+
+/* Training targets, d_y [E][np_coarse] FP32 device array (the element's
+ * value on each of its nodes, row-aligned with sel_closure_features):
+ * u-bar = P(u), tau_sgs = P(u u) - u-bar u-bar with P the projection above,
+ * S-bar the strain rate of u-bar on the coarse element,
+ * nu_t = max(0, -<dev tau_sgs : S-bar> / <2 S-bar : S-bar>) with wJ-weighted
+ * element sums, dtau* = nu_t / (c_s^2 dt_coarse) and y = dtau* / tau_coarse
+ * (the target of softplus(z)). Synchronises. */
+int sel_closure_targets(const sel_sim *fine, sel_sim *coarse, float *d_y);
+
+/* Inference on n feature rows d_X [n][6] (device): z [n] and dtau [n] (either
+ * may be NULL) for relaxation time tau. Enqueued on stream (hipStream_t). */
+int sel_mlp_forward(const float *d_params, const float *d_X, int64_t n, double tau, float *d_z,
+                    float *d_dtau, void *stream);
+
+/* Floats of device work memory sel_mlp_train_step / sel_mlp_gradient need
+ * for n rows. */
+int64_t sel_mlp_work_floats(int64_t n);
+
+/* Loss L = mean_i (softplus(z_i) - y_i)^2 over n rows (targets y = dtau/tau)
+ * and its gradient with respect to the trainable range, d_grad [8833].
+ * Row i is row d_idx[i] of d_X [.][6] and d_y (d_idx: device int32 [n], or
+ * NULL for rows 0..n-1; the caller keeps indices in range). The gradient
+ * sums over rows in index order (deterministic). loss (host, may be NULL)
+ * synchronises. */
+int sel_mlp_gradient(const float *d_params, const float *d_X, const float *d_y, const int32_t *d_idx, int64_t n,
+                     float *d_work, float *d_grad, double *loss, void *stream);
+
+/* One Adam step (Kingma and Ba, bias-corrected, step t >= 1) on the
+ * trainable range of d_params with moment buffers d_m, d_v [8833]; loss as
+ * for sel_mlp_gradient, evaluated before the update. */
+int sel_mlp_train_step(float *d_params, float *d_m, float *d_v, const float *d_X, const float *d_y,
+                       const int32_t *d_idx, int64_t n, int64_t t, double lr, double b1, double b2, double eps, float *d_work, double *loss,
+                       void *stream);
 
 /* Thread-local message of the last failing call ("" if none). */
 const char *sel_last_error(void);

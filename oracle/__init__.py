@@ -71,6 +71,7 @@ def _load():
     lib.oracle_legendre.argtypes = [I, D, P, P]
     lib.oracle_rk_scalar.argtypes = [I, D, D, D, D, I64, P]
     lib.oracle_set_threads.argtypes = [I]
+    lib.oracle_set_dtau.argtypes = [P, P]
     lib.oracle_get_threads.restype = I
     _lib = lib
     return lib
@@ -165,6 +166,7 @@ class OracleSim:
                  filter=None, filter_kc=2, filter_amp=0.0, filter_order=2.0, rk="ssprk3"):
         lib = _load()
         self.dim, self.N, self.Q = dim, N, Q
+        self.nu, self.dt, self.rho0 = float(nu), float(dt), float(rho0)
         self.np_ = (N + 1) ** dim
         self._xyz = _f64(xyz)
         self.E = self._xyz.shape[0]

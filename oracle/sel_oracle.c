@@ -313,6 +313,7 @@ typedef struct oracle_sim {
     double *rt;       /* [E][Q][np] element contributions */
     double *rg;       /* [Q][E np] assembled sums by global id */
     double *rhoc;     /* [E][np] density at the collision of the step */
+    double *dtau;     /* [E][np] relaxation-time increments (learned closure), NULL = 0 */
     double time;
     int64_t nstep;
 } oracle_sim;
@@ -480,6 +481,7 @@ void oracle_destroy(oracle_sim *s)
     free(s->rt);
     free(s->rg);
     free(s->rhoc);
+    free(s->dtau);
     free(s);
 }
 
@@ -663,12 +665,14 @@ static void or_collide_all(const oracle_sim *s, const double *fb, double *fs, do
             double rho, u[3], F[3];
             or_moments_node(s, fn, np, &rho, u);
             for (int k = 0; k < 3; ++k) F[k] = rho * s->g[k];
+            /* relaxation time, plus the closure's increment when one is set */
+            double tau = s->tau + (s->dtau ? s->dtau[el * np + p] : 0.0);
             for (int a = 0; a < Q; ++a) {
                 double fss = or_fss(s, a, u, F);
                 double fbeq = or_feq(s, a, rho, u) - 0.5 * s->dt * fss;
                 double fa = fn[(int64_t)a * np];
                 fs[el * (int64_t)Q * np + (int64_t)a * np + p] =
-                    fa - (fa - fbeq) / (s->tau + 0.5) + s->dt * fss;
+                    fa - (fa - fbeq) / (tau + 0.5) + s->dt * fss;
             }
             if (rhoc) rhoc[el * np + p] = rho;
         }
@@ -1002,5 +1006,21 @@ int oracle_rk_scalar(int rk, double lam, double b, double y0, double dt, int64_t
         }
     }
     *y = v;
+    return 0;
+}
+
+/* Per-node relaxation-time increments [E][np] used by the following
+ * collisions (learned closure); NULL or all zero restores the plain method. */
+int oracle_set_dtau(oracle_sim *s, const double *dtau)
+{
+    int64_t nl = s->E * s->np;
+    if (!dtau) {
+        free(s->dtau);
+        s->dtau = NULL;
+        return 0;
+    }
+    if (!s->dtau) s->dtau = (double *)malloc(sizeof(double) * nl);
+    if (!s->dtau) return -1;
+    memcpy(s->dtau, dtau, sizeof(double) * nl);
     return 0;
 }

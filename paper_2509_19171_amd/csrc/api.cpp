@@ -41,8 +41,9 @@ constexpr size_t kAlign = 256;
 struct Plan {
     size_t total = 0;
     size_t tabD, tabF, tabW, geoD, geoW, pcode, bpos, xyz, wJ, J, Gm, invw, invMb, bmap, bown, goff, gmem, ftag,
-        wallu, f[4], rtb, rhoc, io, red, flag;
+        wallu, f[4], rtb, rhoc, io, red, flag, cl_params = 0, cl_X = 0, cl_dtau = 0;
     int nred = 0;
+    bool closure = false;
 };
 
 size_t carve(size_t &cur, size_t bytes)
@@ -87,9 +88,9 @@ int check_params(const sel_mesh *m, const sel_params *p)
         set_error("the printed four-stage form is not built into the device path");
         return SEL_EUNSUPPORTED;
     }
-    if (p->closure != nullptr) {
-        set_error("closure weights are not accepted by this build");
-        return SEL_EUNSUPPORTED;
+    if (p->closure != nullptr && p->closure_len != sel_closure_len()) {
+        set_error("closure_len must equal sel_closure_len()");
+        return SEL_EINVAL;
     }
     if (!sel::find_ops(m->dim, m->N, p->Q, p->precision)) {
         set_error("order N not compiled for this dim/Q/precision");
@@ -134,6 +135,12 @@ Plan make_plan(const sel_mesh *m, const sel_params *p)
     L.nred = (int)nred;
     L.red = carve(c, 8 * (size_t)(8 * nred + 8));
     L.flag = carve(c, 16);
+    if (p->closure != nullptr) {
+        L.closure = true;
+        L.cl_params = carve(c, 4 * (size_t)sel_closure_len());
+        L.cl_X = carve(c, 4 * 6 * (size_t)Gtot);
+        L.cl_dtau = carve(c, 4 * (size_t)Gtot);
+    }
     L.total = (c + kAlign - 1) / kAlign * kAlign;
     return L;
 }
@@ -302,6 +309,12 @@ extern "C" int sel_init(const sel_mesh *m, const sel_params *p, const double *rh
     s->nred = L.nred;
     s->flag = reinterpret_cast<int32_t *>(b + L.flag);
     s->cur = 0;
+    if (L.closure) {
+        s->closure_space = true;
+        s->cl_params = reinterpret_cast<float *>(b + L.cl_params);
+        s->cl_X = reinterpret_cast<float *>(b + L.cl_X);
+        s->cl_dtau = reinterpret_cast<float *>(b + L.cl_dtau);
+    }
 
     auto fail = [&](int rc) {
         hipStreamSynchronize(s->stream);
@@ -332,6 +345,14 @@ extern "C" int sel_init(const sel_mesh *m, const sel_params *p, const double *rh
     for (int i = 0; i < 4; ++i)
         if (hipMemsetAsync(s->f[i], 0, s->tsize * s->nstate, s->stream) != hipSuccess) return fail(SEL_EDEVICE);
     if (hipMemsetAsync(s->rhoc, 0, s->tsize * s->Gtot, s->stream) != hipSuccess) return fail(SEL_EDEVICE);
+    if (L.closure) {
+        if (hipMemsetAsync(s->cl_X, 0, 4 * 6 * s->Gtot, s->stream) != hipSuccess ||
+            hipMemsetAsync(s->cl_dtau, 0, 4 * s->Gtot, s->stream) != hipSuccess ||
+            hipMemcpyAsync(s->cl_params, p->closure, 4 * p->closure_len, hipMemcpyHostToDevice, s->stream) !=
+                hipSuccess)
+            return fail(SEL_EDEVICE);
+        s->closure_on = true;
+    }
     if ((rc = ops->geometry(s))) return fail(rc);
     if ((rc = ops->mass(s))) return fail(rc);
     if ((rc = ops->init(s, s->io, s->io + nl))) return fail(rc);

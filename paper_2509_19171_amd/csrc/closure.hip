@@ -1,0 +1,763 @@
+// Learned relaxation-time closure: MLP inference (FP32 MFMA), training
+// kernels (forward, backward, deterministic weight-gradient sums, Adam),
+// coarse graining of a fine simulation onto a coarse one of the same
+// elements, training targets, and their C entry points.
+//
+// Parameter blob (float32): mean[6], std[6], W1[64][6], b1[64], W2[64][64],
+// b2[64], W3[64][64], b3[64], w4[64], b4[1], dtau_max[1]. The trainable
+// parameters are the contiguous range W1 .. b4.
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "kernels_impl.h"
+#include "ops.h"
+
+namespace sel {
+
+namespace {
+
+constexpr int NF = 6, NH = 64;
+constexpr int OFF_MEAN = 0, OFF_STD = 6, OFF_W1 = 12, OFF_B1 = OFF_W1 + NH * NF, OFF_W2 = OFF_B1 + NH,
+              OFF_B2 = OFF_W2 + NH * NH, OFF_W3 = OFF_B2 + NH, OFF_B3 = OFF_W3 + NH * NH, OFF_W4 = OFF_B3 + NH,
+              OFF_B4 = OFF_W4 + NH, OFF_DMAX = OFF_B4 + 1, BLOB = OFF_DMAX + 1;
+constexpr int OFF_TRAIN = OFF_W1, NTRAIN = OFF_DMAX - OFF_W1;  // 8833
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float softplusf(float z) { return fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))); }
+
+__device__ __forceinline__ float guard_dtau(float d, float tau, float dmax)
+{
+    // fallback to the plain method (0) for non-finite or out-of-range values
+    return (d == d && d >= 0.f && d <= dmax * tau) ? d : 0.f;
+}
+
+// ------------------------------------------------------------ inference --
+// One workgroup of 4 wavefronts; each wavefront runs a tile of 64 rows
+// through 6 -> 64 -> 64 -> 64 -> 1 with v_mfma_f32_16x16x4f32 for the three
+// hidden layers (A = activations, B = W^T, 4 x 4 output tiles of 16 x 16,
+// activations re-laid out through LDS between layers).
+__global__ void __launch_bounds__(256) k_mlp_infer(const float *__restrict__ P, const float *__restrict__ X,
+                                                   int64_t n, float tau, float *__restrict__ zout,
+                                                   float *__restrict__ dtau)
+{
+    __shared__ float sW1[NH][9];
+    __shared__ float sW2[NH][NH + 1];
+    __shared__ float sW3[NH][NH + 1];
+    __shared__ float sb1[NH], sb2[NH], sb3[NH], sw4[NH];
+    __shared__ float sH[4][64][NH + 1];
+    __shared__ float smean[NF], sistd[NF];
+    const int tid = threadIdx.x;
+    for (int q = tid; q < NH * 8; q += 256) {
+        const int r = q / 8, c = q % 8;
+        sW1[r][c] = (c < NF) ? P[OFF_W1 + r * NF + c] : 0.f;
+    }
+    for (int q = tid; q < NH * NH; q += 256) {
+        sW2[q / NH][q % NH] = P[OFF_W2 + q];
+        sW3[q / NH][q % NH] = P[OFF_W3 + q];
+    }
+    if (tid < NH) {
+        sb1[tid] = P[OFF_B1 + tid];
+        sb2[tid] = P[OFF_B2 + tid];
+        sb3[tid] = P[OFF_B3 + tid];
+        sw4[tid] = P[OFF_W4 + tid];
+    }
+    if (tid < NF) {
+        smean[tid] = P[OFF_MEAN + tid];
+        sistd[tid] = 1.f / P[OFF_STD + tid];
+    }
+    __syncthreads();
+    const float b4 = P[OFF_B4], dmax = P[OFF_DMAX];
+    const int w = tid / 64, l = tid % 64;
+    const int li = l & 15, lk = l >> 4;
+    for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += (int64_t)gridDim.x * 256) {
+        const int64_t r = base + w * 64 + l;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) sH[w][l][c] = (c < NF && r < n) ? (X[r * NF + c] - smean[c]) * sistd[c] : 0.f;
+        __syncthreads();
+        f4 acc[4][4];
+        // hidden layer 1 (K = 8, zero padded)
+#pragma unroll
+        for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            float a[4], b[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                a[t] = sH[w][16 * t + li][4 * ks + lk];
+                b[t] = sW1[16 * t + li][4 * ks + lk];
+            }
+#pragma unroll
+            for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < 4; ++tj)
+                    acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int col = 16 * tj + li;
+                    sH[w][16 * ti + 4 * lk + q][col] = tanhf(acc[ti][tj][q] + sb1[col]);
+                }
+        __syncthreads();
+        // hidden layers 2 and 3 (K = 64)
+#pragma unroll
+        for (int layer = 0; layer < 2; ++layer) {
+            const float(*Wl)[NH + 1] = layer == 0 ? sW2 : sW3;
+            const float *bl = layer == 0 ? sb2 : sb3;
+#pragma unroll
+            for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = f4{0.f, 0.f, 0.f, 0.f};
+            for (int ks = 0; ks < NH / 4; ++ks) {
+                float a[4], b[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    a[t] = sH[w][16 * t + li][4 * ks + lk];
+                    b[t] = Wl[16 * t + li][4 * ks + lk];
+                }
+#pragma unroll
+                for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < 4; ++tj)
+                        acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int col = 16 * tj + li;
+                        sH[w][16 * ti + 4 * lk + q][col] = tanhf(acc[ti][tj][q] + bl[col]);
+                    }
+            __syncthreads();
+        }
+        // output layer
+        float z = b4;
+#pragma unroll 8
+        for (int c = 0; c < NH; ++c) z += sH[w][l][c] * sw4[c];
+        if (r < n) {
+            if (zout) zout[r] = z;
+            if (dtau) dtau[r] = guard_dtau(tau * softplusf(z), tau, dmax);
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------- training --
+// Work layout (floats): Xn[n][8], H1, H2, H3, D1, D2, D3 [n][64], Z[n], DZ[n],
+// grad[NTRAIN], loss partials [nblk].
+struct TrainWork {
+    float *Xn, *H1, *H2, *H3, *D1, *D2, *D3, *Z, *DZ, *grad, *part;
+};
+
+TrainWork carve_work(float *w, int64_t n)
+{
+    TrainWork t;
+    t.Xn = w;
+    t.H1 = t.Xn + 8 * n;
+    t.H2 = t.H1 + NH * n;
+    t.H3 = t.H2 + NH * n;
+    t.D1 = t.H3 + NH * n;
+    t.D2 = t.D1 + NH * n;
+    t.D3 = t.D2 + NH * n;
+    t.Z = t.D3 + NH * n;
+    t.DZ = t.Z + n;
+    t.grad = t.DZ + n;
+    t.part = t.grad + NTRAIN;
+    return t;
+}
+
+int64_t train_blocks(int64_t n) { return (n + 255) / 256; }
+
+// dense layer of one sample: out[c] = tanh(b[c] + sum_k W[c][k] in[k]), in registers
+template <int K>
+__device__ __forceinline__ void dense_tanh(const float *__restrict__ W, const float *__restrict__ b, const float (&in)[K],
+                                           float *__restrict__ out_row)
+{
+    for (int c = 0; c < NH; ++c) {
+        float s = b[c];
+#pragma unroll
+        for (int k = 0; k < K; ++k) s += W[c * K + k] * in[k];
+        out_row[c] = tanhf(s);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_train_fwd(const float *__restrict__ P, const float *__restrict__ X,
+                                                   const int32_t *__restrict__ idx, int64_t n, TrainWork T)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int64_t row = idx ? (int64_t)idx[s] : s;
+    float x[NF];
+#pragma unroll
+    for (int c = 0; c < NF; ++c) {
+        x[c] = (X[row * NF + c] - P[OFF_MEAN + c]) / P[OFF_STD + c];
+        T.Xn[s * 8 + c] = x[c];
+    }
+    dense_tanh<NF>(P + OFF_W1, P + OFF_B1, x, T.H1 + s * NH);
+    float h[NH];
+#pragma unroll
+    for (int c = 0; c < NH; ++c) h[c] = T.H1[s * NH + c];
+    dense_tanh<NH>(P + OFF_W2, P + OFF_B2, h, T.H2 + s * NH);
+#pragma unroll
+    for (int c = 0; c < NH; ++c) h[c] = T.H2[s * NH + c];
+    dense_tanh<NH>(P + OFF_W3, P + OFF_B3, h, T.H3 + s * NH);
+    float z = P[OFF_B4];
+#pragma unroll
+    for (int c = 0; c < NH; ++c) z += P[OFF_W4 + c] * T.H3[s * NH + c];
+    T.Z[s] = z;
+}
+
+// back-propagation of the mean squared error of softplus(z) against y
+__global__ void __launch_bounds__(256) k_train_bwd(const float *__restrict__ P, const float *__restrict__ y,
+                                                   const int32_t *__restrict__ idx, int64_t n, TrainWork T)
+{
+    __shared__ float red[256];
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float r2 = 0.f;
+    if (s < n) {
+        const float z = T.Z[s];
+        const float r = softplusf(z) - y[idx ? (int64_t)idx[s] : s];
+        r2 = r * r;
+        const float dz = (2.f / float(n)) * r / (1.f + expf(-z));
+        T.DZ[s] = dz;
+        float d[NH];
+#pragma unroll
+        for (int c = 0; c < NH; ++c) {
+            const float h = T.H3[s * NH + c];
+            d[c] = dz * P[OFF_W4 + c] * (1.f - h * h);
+            T.D3[s * NH + c] = d[c];
+        }
+        for (int k = 0; k < NH; ++k) {  // D2 = (W3^T D3) (1 - H2^2)
+            float a = 0.f;
+#pragma unroll
+            for (int c = 0; c < NH; ++c) a += P[OFF_W3 + c * NH + k] * d[c];
+            const float h = T.H2[s * NH + k];
+            T.D2[s * NH + k] = a * (1.f - h * h);
+        }
+#pragma unroll
+        for (int c = 0; c < NH; ++c) d[c] = T.D2[s * NH + c];
+        for (int k = 0; k < NH; ++k) {  // D1 = (W2^T D2) (1 - H1^2)
+            float a = 0.f;
+#pragma unroll
+            for (int c = 0; c < NH; ++c) a += P[OFF_W2 + c * NH + k] * d[c];
+            const float h = T.H1[s * NH + k];
+            T.D1[s * NH + k] = a * (1.f - h * h);
+        }
+    }
+    red[threadIdx.x] = r2;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) T.part[blockIdx.x] = red[0];
+}
+
+// one thread per trainable parameter; sums over samples in index order
+__global__ void __launch_bounds__(256) k_train_wgrad(int64_t n, TrainWork T)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= NTRAIN) return;
+    const int o = q + OFF_TRAIN;
+    const float *D, *Aa;
+    int m, k, K;
+    bool bias = false;
+    if (o < OFF_B1) { D = T.D1; Aa = T.Xn; K = 8; m = (o - OFF_W1) / NF; k = (o - OFF_W1) % NF; }
+    else if (o < OFF_W2) { D = T.D1; Aa = nullptr; K = 0; m = o - OFF_B1; k = 0; bias = true; }
+    else if (o < OFF_B2) { D = T.D2; Aa = T.H1; K = NH; m = (o - OFF_W2) / NH; k = (o - OFF_W2) % NH; }
+    else if (o < OFF_W3) { D = T.D2; Aa = nullptr; K = 0; m = o - OFF_B2; k = 0; bias = true; }
+    else if (o < OFF_B3) { D = T.D3; Aa = T.H2; K = NH; m = (o - OFF_W3) / NH; k = (o - OFF_W3) % NH; }
+    else if (o < OFF_W4) { D = T.D3; Aa = nullptr; K = 0; m = o - OFF_B3; k = 0; bias = true; }
+    else if (o < OFF_B4) { D = T.DZ; Aa = T.H3; K = NH; m = 0; k = o - OFF_W4; }
+    else { D = T.DZ; Aa = nullptr; K = 0; m = 0; k = 0; bias = true; }
+    const int Dstride = (D == T.DZ) ? 1 : NH;
+    float g = 0.f;
+    for (int64_t s = 0; s < n; ++s) {
+        const float dv = D[s * Dstride + m];
+        g += bias ? dv : dv * Aa[s * K + k];
+    }
+    T.grad[q] = g;
+}
+
+__global__ void k_train_loss(const float *part, int nb, int64_t n, float *out)
+{
+    if (threadIdx.x != 0) return;
+    float s = 0.f;
+    for (int b = 0; b < nb; ++b) s += part[b];
+    out[0] = s / float(n);
+}
+
+// Adam (Kingma & Ba), bias-corrected, on the trainable range
+__global__ void k_adam(float *P, float *m, float *v, const float *g, int64_t t, float lr, float b1, float b2, float eps)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= NTRAIN) return;
+    const float gq = g[q];
+    const float mq = b1 * m[q] + (1.f - b1) * gq;
+    const float vq = b2 * v[q] + (1.f - b2) * gq * gq;
+    m[q] = mq;
+    v[q] = vq;
+    const float mh = mq / (1.f - powf(b1, float(t)));
+    const float vh = vq / (1.f - powf(b2, float(t)));
+    P[OFF_TRAIN + q] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+// --------------------------------------------------------- coarse graining --
+// One workgroup per element, one thread per fine node; the projection matrix
+// Pm[ic][jf] is applied along r, s (and t) through LDS (sizes change per pass).
+template <int DIM, int Q, typename T, bool DEV>
+__global__ void k_coarse(NodeMap Mf, const T *ff, NodeMap Mc, T *fc, const double *Pm, int nf1, int nc1, double rho0)
+{
+    __shared__ double b0[1024], b1[1024];
+    __shared__ double sP[kMaxN1 * kMaxN1];
+    const int64_t e = blockIdx.x;
+    const int p = threadIdx.x;
+    const int npf = blockDim.x;
+    for (int q = p; q < nc1 * nf1; q += npf) sP[q] = Pm[q];
+    const int i = p % nf1, j = (p / nf1) % nf1, k = (DIM == 3) ? p / (nf1 * nf1) : 0;
+    bool ownf;
+    const SIdx sf = Mf.sidx(e, p, ownf);
+    bool ownc = false;
+    SIdx sc{0, 0};
+    const bool on_coarse = i < nc1 && j < nc1 && (DIM == 2 || k < nc1);
+    if (on_coarse) sc = Mc.sidx(e, i + nc1 * j + (DIM == 3 ? nc1 * nc1 * k : 0), ownc);
+    for (int a = 0; a < Q; ++a) {
+        b0[p] = double(ff[sf.base + (int64_t)a * sf.stride]);
+        __syncthreads();
+        if (i < nc1) {  // along r: [nc1][nf1][nf1]
+            double v = 0.0;
+            for (int c = 0; c < nf1; ++c) v += sP[i * nf1 + c] * b0[c + nf1 * j + nf1 * nf1 * k];
+            b1[i + nc1 * j + nc1 * nf1 * k] = v;
+        }
+        __syncthreads();
+        double v = 0.0;
+        if (i < nc1 && j < nc1) {  // along s: [nc1][nc1][nf1]
+            for (int c = 0; c < nf1; ++c) v += sP[j * nf1 + c] * b1[i + nc1 * c + nc1 * nf1 * k];
+        }
+        if (DIM == 3) {
+            __syncthreads();
+            if (i < nc1 && j < nc1) b0[i + nc1 * j + nc1 * nc1 * k] = v;
+            __syncthreads();
+            if (on_coarse) {
+                v = 0.0;
+                for (int c = 0; c < nf1; ++c) v += sP[k * nf1 + c] * b0[i + nc1 * j + nc1 * nc1 * c];
+            }
+        }
+        if (on_coarse && ownc) fc[sc.base + (int64_t)a * sc.stride] = T(v);
+        __syncthreads();
+    }
+    (void)rho0;
+}
+
+// Training target per coarse element: P(u), P(u u) from the fine state,
+// S-bar from P(u) with the coarse metric, tau_sgs = P(uu) - P(u) P(u),
+// nu_t = max(0, -<dev tau_sgs : S-bar> / <2 S-bar : S-bar>), dtau* = nu_t / (c_s^2 dt),
+// written as y = dtau* / tau (the target of softplus(z)) on every coarse node.
+template <int DIM, int Q, typename T, bool DEV>
+__global__ void k_targets(NodeMap Mf, const T *ff, const double *Pm, int nf1, int nc1, const T *Gmc,
+                          const double *wJc, const double *Dc, double rho0, double dtc, double tauc, float *y)
+{
+    constexpr int NFLD = DIM + DIM * (DIM + 1) / 2;
+    __shared__ double b0[1024], b1[1024];
+    __shared__ double sP[kMaxN1 * kMaxN1];
+    __shared__ double cf[NFLD][512];
+    const int64_t e = blockIdx.x;
+    const int p = threadIdx.x;
+    const int npf = blockDim.x;
+    const int ncp = (DIM == 3) ? nc1 * nc1 * nc1 : nc1 * nc1;
+    for (int q = p; q < nc1 * nf1; q += npf) sP[q] = Pm[q];
+    const int i = p % nf1, j = (p / nf1) % nf1, k = (DIM == 3) ? p / (nf1 * nf1) : 0;
+    bool own;
+    const SIdx sf = Mf.sidx(e, p, own);
+    double m = 0, jv[3] = {0, 0, 0};
+    static_for<0, Q>([&](auto AA) {
+        constexpr int a = decltype(AA)::value;
+        const double v = double(ff[sf.base + (int64_t)a * sf.stride]);
+        m += v;
+        if constexpr (lat_e<DIM, Q>(a, 0) != 0) jv[0] += lat_e<DIM, Q>(a, 0) * v;
+        if constexpr (lat_e<DIM, Q>(a, 1) != 0) jv[1] += lat_e<DIM, Q>(a, 1) * v;
+        if constexpr (lat_e<DIM, Q>(a, 2) != 0) jv[2] += lat_e<DIM, Q>(a, 2) * v;
+    });
+    const double rho = DEV ? rho0 + m : m;
+    double fld[NFLD];
+    for (int c = 0; c < DIM; ++c) fld[c] = jv[c] / rho;
+    {
+        int q = DIM;
+        for (int r = 0; r < DIM; ++r)
+            for (int c = r; c < DIM; ++c) fld[q++] = fld[r] * fld[c];
+    }
+    const bool on_coarse = i < nc1 && j < nc1 && (DIM == 2 || k < nc1);
+    const int pc = i + nc1 * j + (DIM == 3 ? nc1 * nc1 * k : 0);
+    for (int q = 0; q < NFLD; ++q) {
+        b0[p] = fld[q];
+        __syncthreads();
+        if (i < nc1) {
+            double v = 0.0;
+            for (int c = 0; c < nf1; ++c) v += sP[i * nf1 + c] * b0[c + nf1 * j + nf1 * nf1 * k];
+            b1[i + nc1 * j + nc1 * nf1 * k] = v;
+        }
+        __syncthreads();
+        double v = 0.0;
+        if (i < nc1 && j < nc1)
+            for (int c = 0; c < nf1; ++c) v += sP[j * nf1 + c] * b1[i + nc1 * c + nc1 * nf1 * k];
+        if (DIM == 3) {
+            __syncthreads();
+            if (i < nc1 && j < nc1) b0[i + nc1 * j + nc1 * nc1 * k] = v;
+            __syncthreads();
+            if (on_coarse) {
+                v = 0.0;
+                for (int c = 0; c < nf1; ++c) v += sP[k * nf1 + c] * b0[i + nc1 * j + nc1 * nc1 * c];
+            }
+        }
+        if (on_coarse) cf[q][pc] = v;
+        __syncthreads();
+    }
+    double num = 0.0, den = 0.0;
+    if (on_coarse) {
+        const int idx[3] = {i, j, k};
+        const int str[3] = {1, nc1, nc1 * nc1};
+        double du[3][3] = {};
+        for (int mm = 0; mm < DIM; ++mm) {
+            const int b = pc - idx[mm] * str[mm];
+            for (int c = 0; c < nc1; ++c) {
+                const double dq = Dc[idx[mm] * nc1 + c];
+                for (int q = 0; q < DIM; ++q) du[q][mm] += dq * cf[q][b + c * str[mm]];
+            }
+        }
+        const double wj = wJc[e * ncp + pc];
+        double A[3][3] = {};
+        for (int mm = 0; mm < DIM; ++mm)
+            for (int q = 0; q < DIM; ++q) {
+                const double drdx = double(Gmc[(e * DIM * DIM + mm * DIM + q) * ncp + pc]) / wj;
+                for (int c = 0; c < DIM; ++c) A[c][q] += du[c][mm] * drdx;
+            }
+        double S[3][3] = {}, tau[3][3] = {};
+        int q = DIM;
+        for (int r = 0; r < DIM; ++r)
+            for (int c = r; c < DIM; ++c) {
+                tau[r][c] = tau[c][r] = cf[q][pc] - cf[r][pc] * cf[c][pc];
+                ++q;
+            }
+        double tr = 0.0;
+        for (int r = 0; r < DIM; ++r) tr += tau[r][r];
+        for (int r = 0; r < DIM; ++r)
+            for (int c = 0; c < DIM; ++c) {
+                S[r][c] = 0.5 * (A[r][c] + A[c][r]);
+                const double td = tau[r][c] - (r == c ? tr / DIM : 0.0);
+                num += wj * td * S[r][c];
+                den += wj * 2.0 * S[r][c] * S[r][c];
+            }
+    }
+    b0[p] = num;  // b0 and b1 are free after the last pass
+    b1[p] = den;
+    __syncthreads();
+    if (p == 0) {
+        double sn = 0.0, sd = 0.0;
+        for (int q = 0; q < npf; ++q) {
+            sn += b0[q];
+            sd += b1[q];
+        }
+        const double nut = (sd > 0.0) ? fmax(0.0, -sn / sd) : 0.0;
+        b0[0] = nut / (dtc / 3.0) / tauc;
+    }
+    __syncthreads();
+    if (p < ncp) y[e * ncp + p] = float(b0[0]);
+}
+
+template <int DIM, int Q, typename T, bool DEV>
+NodeMap nodemap_of(const sel_sim *s)
+{
+    NodeMap M;
+    M.pcode = s->pcode;
+    M.bmap = s->bmap;
+    M.bown = s->bown;
+    M.E = s->E;
+    M.Gi = s->Gi;
+    M.QGi = (int64_t)Q * s->Gi;
+    M.NP = s->np;
+    M.NI = s->nint;
+    M.NB = s->nbe;
+    M.Q = Q;
+    return M;
+}
+
+template <int DIM, int Q, typename T, bool DEV>
+int run_coarse(const sel_sim *f, sel_sim *c, const double *dP, bool targets, float *y)
+{
+    const dim3 grid((unsigned)f->E), block((unsigned)f->np);
+    if (!targets) {
+        hipLaunchKernelGGL((k_coarse<DIM, Q, T, DEV>), grid, block, 0, c->stream, nodemap_of<DIM, Q, T, DEV>(f),
+                           static_cast<const T *>(f->f[f->cur]), nodemap_of<DIM, Q, T, DEV>(c),
+                           static_cast<T *>(c->f[c->cur]), dP, f->n1, c->n1, f->p.rho0);
+    } else {
+        hipLaunchKernelGGL((k_targets<DIM, Q, T, DEV>), grid, block, 0, c->stream, nodemap_of<DIM, Q, T, DEV>(f),
+                           static_cast<const T *>(f->f[f->cur]), dP, f->n1, c->n1, static_cast<const T *>(c->Gm),
+                           c->wJ, c->geoD, f->p.rho0, c->p.dt, c->tau, y);
+    }
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) {
+        set_error(std::string("coarse-graining launch failed: ") + hipGetErrorString(err));
+        return SEL_EDEVICE;
+    }
+    return SEL_OK;
+}
+
+int coarse_dispatch(const sel_sim *f, sel_sim *c, const double *dP, bool targets, float *y)
+{
+    const bool f32 = f->prec == SEL_FP32_DEV;
+    if (f->dim == 2 && f->Q == 9)
+        return f32 ? run_coarse<2, 9, float, true>(f, c, dP, targets, y) : run_coarse<2, 9, double, false>(f, c, dP, targets, y);
+    if (f->dim == 3 && f->Q == 27)
+        return f32 ? run_coarse<3, 27, float, true>(f, c, dP, targets, y)
+                   : run_coarse<3, 27, double, false>(f, c, dP, targets, y);
+    if (f->dim == 3 && f->Q == 19)
+        return f32 ? run_coarse<3, 19, float, true>(f, c, dP, targets, y)
+                   : run_coarse<3, 19, double, false>(f, c, dP, targets, y);
+    set_error("coarse graining: unsupported lattice");
+    return SEL_EUNSUPPORTED;
+}
+
+int check_pair(const sel_sim *f, const sel_sim *c)
+{
+    if (!f || !c) {
+        set_error("coarse graining: null simulation");
+        return SEL_EINVAL;
+    }
+    if (f->dim != c->dim || f->Q != c->Q || f->prec != c->prec || f->E != c->E || c->N > f->N) {
+        set_error("coarse graining: simulations must share dim, lattice, storage and elements, coarse N <= fine N");
+        return SEL_EINVAL;
+    }
+    if (f->np > 1024 || c->np > 512) {
+        set_error("coarse graining: order too high (fine np <= 1024, coarse np <= 512)");
+        return SEL_EUNSUPPORTED;
+    }
+    return SEL_OK;
+}
+
+}  // namespace
+
+int launch_mlp_infer(sel_sim *s)
+{
+    const int64_t n = s->Gtot;
+    int64_t nb = (n + 255) / 256;
+    if (nb > 2048) nb = 2048;
+    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)nb), dim3(256), 0, s->stream, s->cl_params, s->cl_X, n,
+                       float(s->tau), nullptr, s->cl_dtau);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) {
+        set_error(std::string("closure inference launch failed: ") + hipGetErrorString(err));
+        return SEL_EDEVICE;
+    }
+    return SEL_OK;
+}
+
+}  // namespace sel
+
+using sel::set_error;
+
+extern "C" int64_t sel_closure_len(void) { return sel::BLOB; }
+
+extern "C" int sel_closure_set(sel_sim *s, const float *params, int64_t len)
+{
+    if (!s) {
+        set_error("sel_closure_set: null sim");
+        return SEL_EINVAL;
+    }
+    if (!params) {
+        s->closure_on = false;
+        return SEL_OK;
+    }
+    if (!s->closure_space) {
+        set_error("sel_closure_set: the simulation was created without closure buffers (pass a blob to sel_init)");
+        return SEL_ESTATE;
+    }
+    if (len != sel::BLOB) {
+        set_error("sel_closure_set: blob length must be sel_closure_len()");
+        return SEL_EINVAL;
+    }
+    if (hipMemcpyAsync(s->cl_params, params, sizeof(float) * len, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess) {
+        set_error("sel_closure_set: upload failed");
+        return SEL_EDEVICE;
+    }
+    s->closure_on = true;
+    return SEL_OK;
+}
+
+extern "C" int sel_closure_features(sel_sim *s, float *d_X)
+{
+    if (!s || !d_X) {
+        set_error("sel_closure_features: null argument");
+        return SEL_EINVAL;
+    }
+    return sel::find_ops(s->dim, s->N, s->Q, s->prec)->features(s, d_X, 0);
+}
+
+extern "C" int sel_closure_dtau(sel_sim *s, float *d_dtau)
+{
+    if (!s || !d_dtau) {
+        set_error("sel_closure_dtau: null argument");
+        return SEL_EINVAL;
+    }
+    if (!s->closure_on) {
+        set_error("sel_closure_dtau: no closure attached");
+        return SEL_ESTATE;
+    }
+    if (int rc = sel::find_ops(s->dim, s->N, s->Q, s->prec)->features(s, s->cl_X, 1)) return rc;
+    if (int rc = sel::launch_mlp_infer(s)) return rc;
+    if (hipMemcpyAsync(d_dtau, s->cl_dtau, sizeof(float) * s->Gtot, hipMemcpyDeviceToDevice, s->stream) != hipSuccess) {
+        set_error("sel_closure_dtau: copy failed");
+        return SEL_EDEVICE;
+    }
+    return SEL_OK;
+}
+
+static int projection_on_device(const sel_sim *f, const sel_sim *c, double **dP)
+{
+    std::vector<double> Pm((size_t)c->n1 * f->n1);
+    if (sel::build_projection(f->N, c->N, Pm.data())) {
+        set_error("coarse graining: projection table");
+        return SEL_EINVAL;
+    }
+    if (hipMalloc(dP, sizeof(double) * Pm.size()) != hipSuccess) {
+        set_error("coarse graining: allocation failed");
+        return SEL_ENOMEM;
+    }
+    if (hipMemcpyAsync(*dP, Pm.data(), sizeof(double) * Pm.size(), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        hipFree(*dP);
+        set_error("coarse graining: upload failed");
+        return SEL_EDEVICE;
+    }
+    return SEL_OK;
+}
+
+extern "C" int sel_coarse_grain(const sel_sim *fine, sel_sim *coarse)
+{
+    if (int rc = sel::check_pair(fine, coarse)) return rc;
+    double *dP = nullptr;
+    if (int rc = projection_on_device(fine, coarse, &dP)) return rc;
+    int rc = hipStreamSynchronize(fine->stream) == hipSuccess ? SEL_OK : SEL_EDEVICE;
+    if (!rc) rc = sel::coarse_dispatch(fine, coarse, dP, false, nullptr);
+    if (!rc && hipStreamSynchronize(coarse->stream) != hipSuccess) rc = SEL_EDEVICE;
+    hipFree(dP);
+    return rc;
+}
+
+extern "C" int sel_closure_targets(const sel_sim *fine, sel_sim *coarse, float *d_y)
+{
+    if (!d_y) {
+        set_error("sel_closure_targets: null output");
+        return SEL_EINVAL;
+    }
+    if (int rc = sel::check_pair(fine, coarse)) return rc;
+    double *dP = nullptr;
+    if (int rc = projection_on_device(fine, coarse, &dP)) return rc;
+    int rc = hipStreamSynchronize(fine->stream) == hipSuccess ? SEL_OK : SEL_EDEVICE;
+    if (!rc) rc = sel::coarse_dispatch(fine, coarse, dP, true, d_y);
+    if (!rc && hipStreamSynchronize(coarse->stream) != hipSuccess) rc = SEL_EDEVICE;
+    hipFree(dP);
+    return rc;
+}
+
+extern "C" int sel_mlp_forward(const float *d_params, const float *d_X, int64_t n, double tau, float *d_z,
+                               float *d_dtau, void *stream)
+{
+    if (!d_params || !d_X || n < 0) {
+        set_error("sel_mlp_forward: bad argument");
+        return SEL_EINVAL;
+    }
+    if (n == 0) return SEL_OK;
+    int64_t nb = (n + 255) / 256;
+    if (nb > 2048) nb = 2048;
+    hipLaunchKernelGGL(sel::k_mlp_infer, dim3((unsigned)nb), dim3(256), 0, static_cast<hipStream_t>(stream), d_params,
+                       d_X, n, float(tau), d_z, d_dtau);
+    if (hipGetLastError() != hipSuccess) {
+        set_error("sel_mlp_forward: launch failed");
+        return SEL_EDEVICE;
+    }
+    return SEL_OK;
+}
+
+extern "C" int64_t sel_mlp_work_floats(int64_t n)
+{
+    return (8 + 6 * (int64_t)sel::NH + 2) * n + sel::NTRAIN + sel::train_blocks(n) + 1;
+}
+
+extern "C" int sel_mlp_train_step(float *d_params, float *d_m, float *d_v, const float *d_X, const float *d_y,
+                                  const int32_t *d_idx, int64_t n, int64_t t, double lr, double b1, double b2, double eps, float *d_work,
+                                  double *loss, void *stream)
+{
+    if (!d_params || !d_m || !d_v || !d_X || !d_y || !d_work || n < 1 || t < 1) {
+        set_error("sel_mlp_train_step: bad argument");
+        return SEL_EINVAL;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    sel::TrainWork T = sel::carve_work(d_work, n);
+    const int64_t nb = sel::train_blocks(n);
+    float *dloss = T.part + nb;
+    hipLaunchKernelGGL(sel::k_train_fwd, dim3((unsigned)nb), dim3(256), 0, st, d_params, d_X, d_idx, n, T);
+    hipLaunchKernelGGL(sel::k_train_bwd, dim3((unsigned)nb), dim3(256), 0, st, d_params, d_y, d_idx, n, T);
+    hipLaunchKernelGGL(sel::k_train_loss, dim3(1), dim3(64), 0, st, T.part, (int)nb, n, dloss);
+    const unsigned gq = (sel::NTRAIN + 255) / 256;
+    hipLaunchKernelGGL(sel::k_train_wgrad, dim3(gq), dim3(256), 0, st, n, T);
+    hipLaunchKernelGGL(sel::k_adam, dim3(gq), dim3(256), 0, st, d_params, d_m, d_v, T.grad, t, float(lr), float(b1),
+                       float(b2), float(eps));
+    if (hipGetLastError() != hipSuccess) {
+        set_error("sel_mlp_train_step: launch failed");
+        return SEL_EDEVICE;
+    }
+    if (loss) {
+        float h = 0.f;
+        if (hipMemcpyAsync(&h, dloss, sizeof(float), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            set_error("sel_mlp_train_step: device error");
+            return SEL_EDEVICE;
+        }
+        *loss = h;
+    }
+    return SEL_OK;
+}
+
+extern "C" int sel_mlp_gradient(const float *d_params, const float *d_X, const float *d_y, const int32_t *d_idx,
+                                int64_t n, float *d_work, float *d_grad, double *loss, void *stream)
+{
+    if (!d_params || !d_X || !d_y || !d_work || !d_grad || n < 1) {
+        set_error("sel_mlp_gradient: bad argument");
+        return SEL_EINVAL;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    sel::TrainWork T = sel::carve_work(d_work, n);
+    const int64_t nb = sel::train_blocks(n);
+    float *dloss = T.part + nb;
+    hipLaunchKernelGGL(sel::k_train_fwd, dim3((unsigned)nb), dim3(256), 0, st, d_params, d_X, d_idx, n, T);
+    hipLaunchKernelGGL(sel::k_train_bwd, dim3((unsigned)nb), dim3(256), 0, st, d_params, d_y, d_idx, n, T);
+    hipLaunchKernelGGL(sel::k_train_loss, dim3(1), dim3(64), 0, st, T.part, (int)nb, n, dloss);
+    const unsigned gq = (sel::NTRAIN + 255) / 256;
+    hipLaunchKernelGGL(sel::k_train_wgrad, dim3(gq), dim3(256), 0, st, n, T);
+    if (hipMemcpyAsync(d_grad, T.grad, sizeof(float) * sel::NTRAIN, hipMemcpyDeviceToDevice, st) != hipSuccess) {
+        set_error("sel_mlp_gradient: copy failed");
+        return SEL_EDEVICE;
+    }
+    if (loss) {
+        float h = 0.f;
+        if (hipMemcpyAsync(&h, dloss, sizeof(float), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            set_error("sel_mlp_gradient: device error");
+            return SEL_EDEVICE;
+        }
+        *loss = h;
+    }
+    return SEL_OK;
+}

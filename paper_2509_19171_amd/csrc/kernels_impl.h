@@ -182,6 +182,8 @@ struct StageArgs {
     T g[3];
     T fsc[kMaxQ];  // F* per unit density: t_a (e_a . g) / cs2
     int filter;    // M_STAGE1: filter the operand first
+    T tau;                // relaxation time
+    const float *dtau;    // learned-closure increments per node id (nullptr: plain method)
 };
 
 template <int DIM, int N, int Q, typename T, bool DEV, int MODE>
@@ -329,7 +331,9 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_stage(StageArgs<T> A)
     T rho = 0;
     if constexpr (MODE == M_STAGE1) {
         if (valid) {
-            collide_node<DIM, Q, T, DEV>(fq, A.rho0, A.omega, A.dt, A.g, rho);
+            T om = A.omega;
+            if (A.dtau) om = T(1) / (A.tau + T(A.dtau[gix]) + T(0.5));
+            collide_node<DIM, Q, T, DEV>(fq, A.rho0, om, A.dt, A.g, rho);
             if (own) {
                 static_for<0, Q>([&](auto AA) {
                     constexpr int a = decltype(AA)::value;
@@ -517,6 +521,151 @@ __global__ void __launch_bounds__(256) k_group(GroupArgs<T> A)
         const T L = s * invM + A.fsc[a] * rho;
         A.out[ix] = A.ca * A.f0[ix] + A.cb * A.fk[ix] + A.cc * L;
     });
+}
+
+// ------------------------------------------------------ closure features --
+// Per element node (learned closure; the method itself has none): velocity
+// u = sum e f / rho, its element-local gradient A_ck = du_c/dx_k (D-hat along
+// reference lines and the metric dr/dx = G / wJ), S and W the symmetric and
+// skew parts, Pi = sum_a e e (f_a - f^eq_a), lam = nu / c_s^2, and
+//   x = [lam^2 S:S, lam^2 W:W, lam^3 tr S^3, lam^3 tr S W W,
+//        Pi:Pi / (rho c_s^2)^2, lam Pi:S / (rho c_s^2)]  (raw, not normalised).
+// owner_out: one row per node id (owning copy); else one row per element node.
+template <typename T>
+struct FeatArgs {
+    const T *f, *Gm, *D;
+    const double *wJ;
+    const int32_t *pcode, *bmap;
+    const uint8_t *bown;
+    float *X;
+    int64_t E, nblk, Gi, QGi;
+    T rho0, lam;
+    int owner_out;
+};
+
+template <int DIM, int N, int Q, typename T, bool DEV>
+__global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_features(FeatArgs<T> A)
+{
+    using GG = Geo<DIM, N>;
+    constexpr int n1 = GG::n1, NP = GG::NP, NI = GG::NI, NB = GG::NB, EPB = GG::EPB;
+    __shared__ T pl[DIM][EPB * NP];
+    const int tid = threadIdx.x;
+    const int le = tid / NP;
+    const int p = tid - le * NP;
+    const int64_t eb = blockIdx.x;
+    if (eb >= A.nblk) return;
+    const int64_t e = eb * EPB + le;
+    const bool valid = e < A.E;
+    const int i = p % n1, j = (p / n1) % n1, k = (DIM == 3) ? p / (n1 * n1) : 0;
+    const int pc = A.pcode[p];
+    const bool inner = pc >= 0;
+    const int bsl = inner ? 0 : -pc - 1;
+    int64_t gix = 0;
+    bool own = false;
+    SIdx si{0, 0};
+    if (valid) {
+        if (inner) {
+            gix = e * NI + pc;
+            own = true;
+            si = sidx_interior(e, pc, Q, NI);
+        } else {
+            const int64_t g = A.bmap[e * NB + bsl];
+            gix = A.Gi + g;
+            own = A.bown[e * NB + bsl] != 0;
+            si = sidx_group(g, Q, A.QGi);
+        }
+    }
+    T m0 = 0, jv[3] = {0, 0, 0};
+    T fq[Q];
+    static_for<0, Q>([&](auto AA) {
+        constexpr int a = decltype(AA)::value;
+        fq[a] = valid ? A.f[si.base + (int64_t)a * si.stride] : T(0);
+        m0 += fq[a];
+        if constexpr (lat_e<DIM, Q>(a, 0) != 0) jv[0] += T(lat_e<DIM, Q>(a, 0)) * fq[a];
+        if constexpr (lat_e<DIM, Q>(a, 1) != 0) jv[1] += T(lat_e<DIM, Q>(a, 1)) * fq[a];
+        if constexpr (lat_e<DIM, Q>(a, 2) != 0) jv[2] += T(lat_e<DIM, Q>(a, 2)) * fq[a];
+    });
+    const T rho = valid ? (DEV ? A.rho0 + m0 : m0) : T(1);
+    T u[3] = {jv[0] / rho, jv[1] / rho, jv[2] / rho};
+    const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    // non-equilibrium second moment
+    T Pi[3][3] = {};
+    static_for<0, Q>([&](auto AA) {
+        constexpr int a = decltype(AA)::value;
+        constexpr int ex = lat_e<DIM, Q>(a, 0), ey = lat_e<DIM, Q>(a, 1), ez = lat_e<DIM, Q>(a, 2);
+        const T t = T(lat_t<DIM, Q>(a));
+        const T eu = T(ex) * u[0] + T(ey) * u[1] + T(ez) * u[2];
+        const T poly = T(3) * eu + T(4.5) * eu * eu - T(1.5) * uu;
+        const T feq = DEV ? t * (m0 + rho * poly) : t * rho * (T(1) + poly);
+        const T d = fq[a] - feq;
+        const int ev[3] = {ex, ey, ez};
+#pragma unroll
+        for (int r = 0; r < DIM; ++r)
+#pragma unroll
+            for (int c = 0; c < DIM; ++c)
+                if (ev[r] != 0 && ev[c] != 0) Pi[r][c] += T(ev[r] * ev[c]) * d;
+    });
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) pl[c][le * NP + p] = u[c];
+    __syncthreads();
+    if (!valid) return;
+    const int idx[3] = {i, j, k};
+    const int str[3] = {1, n1, n1 * n1};
+    T du[3][3] = {};  // du[c][m] = du_c / dr_m
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) {
+        const int b0 = le * NP + p - idx[m] * str[m];
+#pragma unroll
+        for (int q = 0; q < n1; ++q) {
+            const T dq = A.D[idx[m] * n1 + q];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) du[c][m] += dq * pl[c][b0 + q * str[m]];
+        }
+    }
+    const T iwj = T(1.0 / A.wJ[e * NP + p]);
+    T Am[3][3] = {};  // Am[c][q] = du_c / dx_q
+#pragma unroll
+    for (int m = 0; m < DIM; ++m)
+#pragma unroll
+        for (int q = 0; q < DIM; ++q) {
+            const T drdx = A.Gm[(e * DIM * DIM + m * DIM + q) * NP + p] * iwj;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) Am[c][q] += du[c][m] * drdx;
+        }
+    T S[3][3], W[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            S[r][c] = T(0.5) * (Am[r][c] + Am[c][r]);
+            W[r][c] = T(0.5) * (Am[r][c] - Am[c][r]);
+        }
+    T ss = 0, ww = 0, s3 = 0, sww = 0, pp = 0, ps = 0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            ss += S[r][c] * S[r][c];
+            ww += W[r][c] * W[r][c];
+            pp += Pi[r][c] * Pi[r][c];
+            ps += Pi[r][c] * S[r][c];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                s3 += S[r][c] * S[c][q] * S[q][r];
+                sww += S[r][c] * W[c][q] * W[q][r];
+            }
+        }
+    const T lam = A.lam, rc = rho * T(1.0 / 3.0);
+    const float x[6] = {float(lam * lam * ss), float(lam * lam * ww), float(lam * lam * lam * s3),
+                        float(lam * lam * lam * sww), float(pp / (rc * rc)), float(lam * ps / rc)};
+    if (A.owner_out) {
+        if (own)
+#pragma unroll
+            for (int q = 0; q < 6; ++q) A.X[gix * 6 + q] = x[q];
+    } else {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) A.X[(e * NP + p) * 6 + q] = x[q];
+    }
 }
 
 // ---------------------------------------------------------------- geometry --

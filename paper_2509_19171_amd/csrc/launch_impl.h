@@ -62,6 +62,8 @@ struct Impl {
         for (int a = 0; a < Q; ++a) A.fsc[a] = T(s->fsc[a]);
         A.rtb = static_cast<T *>(s->rtb);
         A.rhoc = static_cast<T *>(s->rhoc);
+        A.tau = T(s->tau);
+        A.dtau = nullptr;
         return A;
     }
 
@@ -166,6 +168,22 @@ struct Impl {
         T *F0 = st(s, 2), *FA = st(s, 3);
         bool pending = false;
         for (int64_t n = 0; n < nsteps; ++n) {
+            if (s->closure_on) {
+                // the closure reads the filtered state: materialise it, then
+                // infer the per-node relaxation-time increments
+                if (pending) {
+                    A.op = st(s, s->cur);
+                    A.out = st(s, s->cur ^ 1);
+                    if (int rc = launch_stage<M_FILTER>(s, A)) return rc;
+                    s->cur ^= 1;
+                    pending = false;
+                }
+                if (int rc = features(s, s->cl_X, 1)) return rc;
+                if (int rc = launch_mlp_infer(s)) return rc;
+                A.dtau = s->cl_dtau;
+            } else {
+                A.dtau = nullptr;
+            }
             T *S = st(s, s->cur), *FB = st(s, s->cur ^ 1);
             // stage 1: f1 = f0 + dt L(f0), f0 = collide(filter(f3_prev) or f-bar)
             A.op = S;
@@ -303,9 +321,34 @@ struct Impl {
         return SEL_EINVAL;
     }
 
+    // closure features of the current state: one row per node id
+    // (owner_out = 1) or per element node
+    static int features(sel_sim *s, float *X, int owner_out)
+    {
+        FeatArgs<T> F{};
+        F.f = st(s, s->cur);
+        F.Gm = static_cast<const T *>(s->Gm);
+        F.D = static_cast<const T *>(s->tabD);
+        F.wJ = s->wJ;
+        F.pcode = s->pcode;
+        F.bmap = s->bmap;
+        F.bown = s->bown;
+        F.X = X;
+        F.E = s->E;
+        F.nblk = nblk(s);
+        F.Gi = s->Gi;
+        F.QGi = (int64_t)Q * s->Gi;
+        F.rho0 = T(s->p.rho0);
+        F.lam = T(s->p.nu * 3.0);
+        F.owner_out = owner_out;
+        hipLaunchKernelGGL((k_features<DIM, N, Q, T, DEV>), dim3((unsigned)F.nblk), dim3(GG::BLOCK), 0, s->stream, F);
+        SEL_LAUNCH_CHECK();
+        return SEL_OK;
+    }
+
     static const Ops *ops()
     {
-        static const Ops o = {geometry, mass, init, step, moments, reduce, scatter, gather, apply};
+        static const Ops o = {geometry, mass, init, step, moments, reduce, scatter, gather, apply, features};
         return &o;
     }
 };

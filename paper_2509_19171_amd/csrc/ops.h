@@ -15,7 +15,11 @@ struct Ops {
     int (*scatter)(sel_sim *, int, const double *, void *, bool);
     int (*gather)(sel_sim *, int, const void *, double *, bool);
     int (*apply)(sel_sim *, int, void *, void *, void *);
+    int (*features)(sel_sim *, float *, int);
 };
+
+// learned-closure inference on the simulation's feature rows (closure.hip)
+int launch_mlp_infer(sel_sim *s);
 
 // one table per compiled (dim, N, Q, storage); nullptr if not compiled
 const Ops *ops_d2_fp64(int N);

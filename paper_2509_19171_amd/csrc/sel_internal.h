@@ -24,6 +24,7 @@ struct Tables {
 };
 int build_gll(int N, Tables &t);
 int build_filter(int N, int type, int kc, double amp, double order, Tables &t);
+int build_projection(int Nf, int Nc, double *Pm);
 
 // Lattice (host copy for the few host computations).
 struct HostLattice {
@@ -101,6 +102,12 @@ struct sel_sim {
     int nred = 0;
     int32_t *flag = nullptr;   // [4] device flags (0: bad Jacobian)
     int cur = 0;               // index of the state array in f[]
+    // learned relaxation-time closure (buffers exist when sel_init got a blob)
+    bool closure_space = false;
+    bool closure_on = false;
+    float *cl_params = nullptr; // [closure blob]
+    float *cl_X = nullptr;      // [Gtot][6] features per node id
+    float *cl_dtau = nullptr;   // [Gtot]
     // optional per-launch timing (sel_step_timed)
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> *timing = nullptr;
 };

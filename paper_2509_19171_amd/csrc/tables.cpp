@@ -143,3 +143,46 @@ int build_lattice(int dim, int Q, HostLattice &L)
 }
 
 }  // namespace sel
+
+namespace sel {
+
+// Projection of an Nf-nodal line onto the Nc-nodal line of the same element
+// (learned-closure coarse graining): expansion in the basis phi_0 = P_0,
+// phi_1 = P_1, phi_k = P_k - P_{k-2} through the discrete Legendre transform,
+// truncation to k <= Nc, evaluation at the Nc GLL nodes. Pm[ic][jf].
+// phi_k vanishes at +-1 for k >= 2 and phi_0, phi_1 are kept, so the end rows
+// are unit vectors; they are set exactly, which keeps coarse face values a
+// function of the fine face values alone (identical on both sides of a face).
+int build_projection(int Nf, int Nc, double *Pm)
+{
+    if (Nc > Nf || Nc < 1) return -1;
+    Tables tf, tc;
+    if (build_gll(Nf, tf) || build_gll(Nc, tc)) return -1;
+    const int nf1 = Nf + 1, nc1 = Nc + 1;
+    double Pf[kMaxN1][kMaxN1], Pc[kMaxN1][kMaxN1];
+    for (int i = 0; i < nf1; ++i) legendre_all(Nf, tf.xi[i], Pf[i]);
+    for (int i = 0; i < nc1; ++i) legendre_all(Nf, tc.xi[i], Pc[i]);
+    for (int j = 0; j < nf1; ++j) {
+        double a[kMaxN1 + 2] = {}, p[kMaxN1 + 2] = {};
+        for (int k = 0; k < nf1; ++k) {
+            double gk = (k < Nf) ? 2.0 / (2.0 * k + 1.0) : 2.0 / Nf;
+            a[k] = tf.w[j] * Pf[j][k] / gk;
+        }
+        for (int k = Nf; k >= 0; --k) p[k] = a[k] + p[k + 2];
+        for (int i = 0; i < nc1; ++i) {
+            double s = 0.0;
+            for (int k = 0; k <= Nc; ++k) {
+                double phi = (k >= 2) ? Pc[i][k] - Pc[i][k - 2] : Pc[i][k];
+                s += p[k] * phi;
+            }
+            Pm[i * nf1 + j] = s;
+        }
+    }
+    for (int j = 0; j < nf1; ++j) {
+        Pm[0 * nf1 + j] = (j == 0) ? 1.0 : 0.0;
+        Pm[Nc * nf1 + j] = (j == Nf) ? 1.0 : 0.0;
+    }
+    return 0;
+}
+
+}  // namespace sel

@@ -78,6 +78,15 @@ def load():
         "sel_apply": [P, I32, P, P],
         "sel_geometry": [P, P, P],
         "sel_destroy": [P],
+        "sel_closure_set": [P, P, I64],
+        "sel_closure_features": [P, P],
+        "sel_closure_dtau": [P, P],
+        "sel_coarse_grain": [P, P],
+        "sel_closure_targets": [P, P, P],
+        "sel_mlp_forward": [P, P, I64, ctypes.c_double, P, P, P],
+        "sel_mlp_gradient": [P, P, P, P, I64, P, P, P, P],
+        "sel_mlp_train_step": [P, P, P, P, P, P, I64, I64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, P, P, P],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -89,6 +98,10 @@ def load():
     lib.sel_version.argtypes = []
     lib.sel_stream.restype = ctypes.c_void_p
     lib.sel_stream.argtypes = [P]
+    lib.sel_closure_len.restype = I64
+    lib.sel_closure_len.argtypes = []
+    lib.sel_mlp_work_floats.restype = I64
+    lib.sel_mlp_work_floats.argtypes = [I64]
     _lib = lib
     return lib
 
@@ -155,7 +168,7 @@ class Mesh:
 
 
 def make_params(Q, nu, dt, rho0=1.0, accel=(0.0, 0.0, 0.0), precision="fp64", filter=None, filter_kc=2,
-                filter_amp=0.0, filter_order=2.0, rk="ssprk3") -> sel_params:
+                filter_amp=0.0, filter_order=2.0, rk="ssprk3", closure=None) -> sel_params:
     p = sel_params()
     p.Q = int(Q)
     p.precision = PRECISIONS[precision]
@@ -172,6 +185,11 @@ def make_params(Q, nu, dt, rho0=1.0, accel=(0.0, 0.0, 0.0), precision="fp64", fi
         p.accel[k] = float(acc[k])
     p.closure = None
     p.closure_len = 0
+    if closure is not None:
+        blob = np.ascontiguousarray(closure, dtype=np.float32).reshape(-1)
+        p._closure_blob = blob  # kept alive with the struct; sel_init copies it
+        p.closure = blob.ctypes.data
+        p.closure_len = blob.size
     return p
 
 
@@ -268,6 +286,35 @@ class Sim:
         _check(self._lib.sel_geometry(self._h, _ptr(wJ), _ptr(J)))
         return wJ, J
 
+    # ---- learned closure --------------------------------------------------
+    def closure_set(self, blob):
+        """Replace the closure blob (None: plain method until the next blob)."""
+        if blob is None:
+            _check(self._lib.sel_closure_set(self._h, None, 0))
+            return
+        b = np.ascontiguousarray(blob, dtype=np.float32).reshape(-1)
+        _check(self._lib.sel_closure_set(self._h, _ptr(b), b.size))
+
+    def closure_features(self):
+        """Features of the current state as a float32 torch tensor [E][np][6]."""
+        import torch
+
+        X = torch.empty((self.E, self.np_, 6), dtype=torch.float32, device=self.device)
+        _check(self._lib.sel_closure_features(self._h, ctypes.c_void_p(X.data_ptr())))
+        return X
+
+    @property
+    def unique_nodes(self):
+        return self.mesh.info()["unique_nodes"]
+
+    def closure_dtau(self):
+        """Increments the next step would use, per unique node id (float32 torch tensor)."""
+        import torch
+
+        d = torch.empty(self.unique_nodes, dtype=torch.float32, device=self.device)
+        _check(self._lib.sel_closure_dtau(self._h, ctypes.c_void_p(d.data_ptr())))
+        return d
+
     @property
     def time(self):
         t = ctypes.c_double()
@@ -289,8 +336,104 @@ def params_from_case(case, precision="fp64") -> sel_params:
                        filter_order=case.filter_order, rk=case.rk)
 
 
-def from_case(case, precision="fp64", device="cuda:0", rho=None, u=None, stream=None) -> Sim:
+def from_case(case, precision="fp64", device="cuda:0", rho=None, u=None, stream=None, closure=None) -> Sim:
     """GPU simulation of a case from the seeded input generators."""
     mesh = Mesh.from_inputs(case.mesh)
     p = params_from_case(case, precision)
+    if closure is not None:
+        blob = np.ascontiguousarray(closure, dtype=np.float32).reshape(-1)
+        p._closure_blob = blob
+        p.closure = blob.ctypes.data
+        p.closure_len = blob.size
     return Sim(mesh, p, case.rho if rho is None else rho, case.u if u is None else u, device=device, stream=stream)
+
+
+# ---- learned closure: coarse graining, targets, network ----------------------
+def closure_len() -> int:
+    return int(load().sel_closure_len())
+
+
+def coarse_grain(fine: Sim, coarse: Sim) -> None:
+    """Project the fine state onto the coarse simulation (same elements)."""
+    _check(load().sel_coarse_grain(fine._h, coarse._h))
+
+
+def closure_targets(fine: Sim, coarse: Sim):
+    """Targets dtau* = nu_t / (c_s^2 dt_coarse), the element value on every
+    coarse node (float32 torch tensor [E][np_coarse])."""
+    import torch
+
+    y = torch.empty((coarse.E, coarse.np_), dtype=torch.float32, device=coarse.device)
+    _check(load().sel_closure_targets(fine._h, coarse._h, ctypes.c_void_p(y.data_ptr())))
+    return y
+
+
+def _dp(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream_of(t, stream):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream(t.device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def mlp_forward(params, X, tau, stream=None):
+    """z and dtau for feature rows X [n][6] (float32 torch tensors on the GPU)."""
+    import torch
+
+    X = X.reshape(-1, 6).contiguous()
+    n = X.shape[0]
+    z = torch.empty(n, dtype=torch.float32, device=X.device)
+    d = torch.empty(n, dtype=torch.float32, device=X.device)
+    _check(load().sel_mlp_forward(_dp(params), _dp(X), n, float(tau), _dp(z), _dp(d), _stream_of(X, stream)))
+    return z, d
+
+
+def mlp_work(n, device):
+    import torch
+
+    return torch.empty(int(load().sel_mlp_work_floats(int(n))), dtype=torch.float32, device=device)
+
+
+def mlp_gradient(params, X, y, idx=None, work=None, stream=None):
+    """(gradient of the trainable range [8833], loss) on the GPU; idx selects rows."""
+    import torch
+
+    X = X.reshape(-1, 6).contiguous()
+    n = X.shape[0] if idx is None else idx.numel()
+    work = mlp_work(n, X.device) if work is None else work
+    g = torch.empty(8833, dtype=torch.float32, device=X.device)
+    loss = ctypes.c_double()
+    _check(load().sel_mlp_gradient(_dp(params), _dp(X), _dp(y), _dp(idx), n, _dp(work), _dp(g),
+                                   ctypes.byref(loss), _stream_of(X, stream)))
+    return g, loss.value
+
+
+class MLPTrainer:
+    """Adam training of a closure blob held in a float32 torch tensor."""
+
+    def __init__(self, params, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        import torch
+
+        self.params = params
+        self.m = torch.zeros(8833, dtype=torch.float32, device=params.device)
+        self.v = torch.zeros_like(self.m)
+        self.t = 0
+        self.lr, self.b1, self.b2, self.eps = lr, b1, b2, eps
+        self._work = None
+
+    def step(self, X, y, idx=None, stream=None, want_loss=True):
+        """One Adam step on rows idx (int32 device tensor) of X, y (all rows if None)."""
+        X = X.reshape(-1, 6).contiguous()
+        n = X.shape[0] if idx is None else idx.numel()
+        if self._work is None or self._work.numel() < load().sel_mlp_work_floats(n):
+            self._work = mlp_work(n, X.device)
+        self.t += 1
+        loss = ctypes.c_double()
+        _check(load().sel_mlp_train_step(_dp(self.params), _dp(self.m), _dp(self.v), _dp(X), _dp(y), _dp(idx), n,
+                                         self.t,
+                                         self.lr, self.b1, self.b2, self.eps, _dp(self._work),
+                                         ctypes.byref(loss) if want_loss else None, _stream_of(X, stream)))
+        return loss.value if want_loss else None
