@@ -70,14 +70,22 @@ def algorithmic_bytes(info, Q, s):
         "stage23": s * (Q * G + 2 * Q * E * ni + Q * E * nb + E * npn * dim * dim + 2 * E * ni),
         "assembly": s * (Q * E * nb + 3 * Q * ng + 2 * ng) + 4 * (E * nb + ng),
         "filter": s * 2 * Q * G,
+        # closure: read the state at every unique node and the metric, write 6 features per node id
+        "features": s * (Q * G + E * npn * dim * dim) + 8 * E * npn + 24 * G,
+        # closure network: read 6 features, write one increment per node id
+        "network": 28 * G,
     }
     return nv, step, per
 
 
-def time_form(case, precision, steps, warmup, torch):
+MLP_FLOP_PER_ROW = 2 * (6 * 64 + 64 * 64 * 2 + 64)  # 17280: three hidden layers and the output
+PEAK_FP32_MATRIX_TFLOPS = 157.3
+
+
+def time_form(case, precision, steps, warmup, torch, closure=None):
     from paper_2509_19171_amd import sel
 
-    sim = sel.from_case(case, precision)
+    sim = sel.from_case(case, precision, closure=closure)
     info = sim.mesh.info()
     sim.step(warmup)
     sim.sync()
@@ -96,6 +104,26 @@ def time_form(case, precision, steps, warmup, torch):
     out = dict(ms_total=ms, ms_per_step=ms / steps, kernels=kern, info=info)
     del sim
     torch.cuda.empty_cache()
+    return out
+
+
+def form_summary(f, nv, info, Q, s):
+    out = {"value": round(nv / (f["ms_per_step"] * 1e-3) / 1e9, 3), "ms_per_step": round(f["ms_per_step"], 5)}
+    kern = f["kernels"]
+    if kern.get("network", (0, 0))[1]:
+        _, _, per = algorithmic_bytes(info, Q, s)
+        fms, fn = kern["features"]
+        mms, mn = kern["network"]
+        G = info["unique_nodes"]
+        out["closure_kernels"] = {
+            "features": {"avg_ms": round(fms / fn, 5),
+                         "algorithmic_GBs": round(per["features"] / (fms / fn * 1e-3) / 1e9, 1)},
+            "network": {"avg_ms": round(mms / mn, 5), "bound": "mfma",
+                        "achieved_TFLOPs": round(MLP_FLOP_PER_ROW * G / (mms / mn * 1e-3) / 1e12, 2),
+                        "peak_TFLOPs": PEAK_FP32_MATRIX_TFLOPS, "dtype": "f32",
+                        "frac": round(MLP_FLOP_PER_ROW * G / (mms / mn * 1e-3) / 1e12 / PEAK_FP32_MATRIX_TFLOPS, 4)},
+            "share_of_step": round((fms / fn + mms / mn) / f["ms_per_step"], 4),
+        }
     return out
 
 
@@ -170,6 +198,13 @@ def main():
         w = args.warmup if prec == args.precision else max(5, args.warmup // 2)
         print(f"[bench] timing {prec}: {w} warmup + {k} steps", file=sys.stderr, flush=True)
         forms[prec] = time_form(case, prec, k, w, torch)
+    if not args.no_other_form:
+        # closure form: same workload, features and network inferred every step
+        # (a seeded untrained network; the cost does not depend on the weights)
+        blob = I.closure_blob(0, mean=[0.0] * 6, std=[1.0] * 6)
+        k, w = max(20, args.steps // 2), max(5, args.warmup // 2)
+        print(f"[bench] timing fp32dev+closure: {w} warmup + {k} steps", file=sys.stderr, flush=True)
+        forms["fp32dev+closure"] = time_form(case, "fp32dev", k, w, torch, closure=blob)
 
     head = forms[args.precision]
     info = head["info"]
@@ -217,11 +252,10 @@ def main():
         "step": {"algorithmic_bytes_per_step": int(step_bytes), "achieved": round(step_gbs, 1),
                  "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(step_gbs / PEAK_HBM_GBS, 4)},
         "kernels": {k: {"ms_total": round(v[0], 4), "launches": v[1],
-                        "avg_ms": round(v[0] / v[1], 5) if v[1] else None,
-                        "algorithmic_GBs": round(per_kind[k] / (v[0] / v[1] * 1e-3) / 1e9, 1) if v[1] else None}
-                    for k, v in kern.items()},
-        "forms": {p: {"value": round(nv / (f["ms_per_step"] * 1e-3) / 1e9, 3),
-                      "ms_per_step": round(f["ms_per_step"], 5)} for p, f in forms.items()},
+                        "avg_ms": round(v[0] / v[1], 5),
+                        "algorithmic_GBs": round(per_kind[k] / (v[0] / v[1] * 1e-3) / 1e9, 1)}
+                    for k, v in kern.items() if v[1]},
+        "forms": {p: form_summary(f, nv, info, case.Q, 4 if p.startswith("fp32") else 8) for p, f in forms.items()},
         "src_hash": src_hash(),
     }
     if not args.no_cpu_baseline:

@@ -129,8 +129,10 @@ int sel_step(sel_sim *sim, int64_t nsteps);
  * time and launches[k] the number of launches of kernel kind k:
  *   0 first-stage element kernel (filter of the previous step, collision,
  *     streaming operator), 1 later-stage element kernel (streaming operator),
- *   2 shared-node assembly, 3 end-of-call filter. */
-#define SEL_NKIND 4
+ *   2 shared-node assembly, 3 end-of-call filter, 4 closure features,
+ *   5 closure network (both only with a closure attached). ms and launches
+ *   hold SEL_NKIND entries. */
+#define SEL_NKIND 6
 int sel_step_timed(sel_sim *sim, int64_t nsteps, double *ms, int64_t *launches);
 
 /* Synchronise the stream; SEL_ENONFINITE if the state holds NaN or Inf. */

@@ -1,0 +1,172 @@
+"""Training and judging the learned relaxation-time closure on the GPU.
+
+Samples come from the solver itself: a fine plain run is coarse-grained onto
+a coarser simulation over the same elements (``sel_coarse_grain``); the
+features of the coarse-grained state (``sel_closure_features``) and the
+per-element eddy-viscosity targets (``sel_closure_targets``) form one
+snapshot. Training runs the library's forward, backward and Adam kernels
+(``sel_mlp_train_step``) on seeded minibatches. The judge starts the coarse
+case from the coarse-grained initial state, runs it with and without the
+closure, and compares both with the coarse-grained fine run.
+
+Only host-side orchestration lives here (loops, seeded permutations, small
+statistics for the input normalisation); every step of the solver, the
+coarse graining and the network runs in the HIP library.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Callable, List
+
+import numpy as np
+
+from . import inputs as I
+from . import sel
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def coarse_pair(make_case: Callable[[int], "I.Case"], Nf: int, Nc: int):
+    """Fine and coarse cases on the same elements with the fine time step
+    (the coarse case's step is stable at the fine one)."""
+    cf = make_case(Nf)
+    cc = make_case(Nc)
+    if cc.E != cf.E:
+        raise ValueError("fine and coarse cases must have the same elements")
+    cc.dt = cf.dt
+    return cf, cc
+
+
+@dataclass
+class Samples:
+    X: object            # float32 device tensor [M][6]
+    y: object            # float32 device tensor [M] (dtau* / tau)
+    times: List[float] = field(default_factory=list)
+
+
+def generate(make_case, Nf: int, Nc: int, nsnap: int, every: int, warm: int = 0, precision: str = "fp32dev",
+             device: str = "cuda:0") -> Samples:
+    """Features and targets from nsnap snapshots of a fine plain run, taken
+    every ``every`` steps after ``warm`` steps."""
+    torch = _torch()
+    cf, cc = coarse_pair(make_case, Nf, Nc)
+    fine = sel.from_case(cf, precision=precision, device=device)
+    coarse = sel.from_case(cc, precision=precision, device=device)
+    Xs, ys, times = [], [], []
+    if warm:
+        fine.step(warm)
+    for _ in range(nsnap):
+        fine.step(every)
+        fine.sync()  # raises on a non-finite state
+        sel.coarse_grain(fine, coarse)
+        Xs.append(coarse.closure_features().reshape(-1, 6))
+        ys.append(sel.closure_targets(fine, coarse).reshape(-1))
+        times.append(fine.time)
+    torch.cuda.synchronize()
+    return Samples(torch.cat(Xs), torch.cat(ys), times)
+
+
+@dataclass
+class TrainResult:
+    blob: np.ndarray
+    train_loss: List[float]
+    val_loss: List[float]
+    steps: int
+
+
+def train(samples: Samples, epochs: int = 20, batch: int = 4096, lr: float = 1e-3, seed: int = 0,
+          val_frac: float = 0.1, dtau_max: float = 100.0) -> TrainResult:
+    """Adam (lr, 0.9, 0.999, 1e-8) on seeded minibatches; a seeded hold-out
+    of val_frac of the rows gives the validation loss after every epoch."""
+    torch = _torch()
+    X, y = samples.X, samples.y
+    M = int(X.shape[0])
+    gen = np.random.Generator(np.random.PCG64(seed))
+    order = gen.permutation(M)
+    nval = max(1, int(M * val_frac))
+    tr_rows, val_rows = order[nval:], order[:nval]
+    Xh = X.cpu().numpy().astype(np.float64)[tr_rows]
+    mean = Xh.mean(0)
+    std = Xh.std(0)
+    std = np.where(std > 0, std, 1.0)
+    blob = I.closure_blob(seed, mean, std, dtau_max=dtau_max)
+    P = torch.from_numpy(blob).to(X.device)
+    trainer = sel.MLPTrainer(P, lr=lr)
+    val_idx = torch.from_numpy(val_rows.astype(np.int32)).to(X.device)
+    tr_idx_h = tr_rows.astype(np.int32)
+    hist_t, hist_v = [], []
+    work = sel.mlp_work(max(batch, nval), X.device)
+    for _ in range(epochs):
+        perm = torch.from_numpy(tr_idx_h[gen.permutation(tr_idx_h.size)]).to(X.device)
+        last = None
+        for b in range(0, perm.numel(), batch):
+            last = trainer.step(X, y, idx=perm[b:b + batch], want_loss=(b + batch >= perm.numel()))
+        hist_t.append(float(last))
+        _, vl = sel.mlp_gradient(P, X, y, idx=val_idx, work=work)
+        hist_v.append(float(vl))
+    return TrainResult(P.cpu().numpy(), hist_t, hist_v, trainer.t)
+
+
+@dataclass
+class Judgement:
+    times: List[float]
+    err_plain: List[float]
+    err_closure: List[float]
+    ke_ref: List[float]
+    ke_plain: List[float]
+    ke_closure: List[float]
+
+    @property
+    def gain(self) -> float:
+        """Mean velocity error of the plain coarse run over that of the closure run."""
+        return float(np.mean(self.err_plain) / max(np.mean(self.err_closure), 1e-300))
+
+    @property
+    def gain_ke(self) -> float:
+        """Mean kinetic-energy error of the plain coarse run over that of the closure run."""
+        r = np.asarray(self.ke_ref)
+        ep = np.abs(np.asarray(self.ke_plain) - r).mean()
+        ec = np.abs(np.asarray(self.ke_closure) - r).mean()
+        return float(ep / max(ec, 1e-300))
+
+
+def _l2(u, uref, wJ):
+    d = ((u - uref) ** 2).sum(-1)
+    r = (uref ** 2).sum(-1)
+    return float(np.sqrt((wJ * d).sum() / max((wJ * r).sum(), 1e-300)))
+
+
+def judge(make_case, Nf: int, Nc: int, blob, nchk: int, every: int, precision: str = "fp32dev",
+          device: str = "cuda:0") -> Judgement:
+    """Coarse runs with and without the closure against the coarse-grained
+    fine run, compared every ``every`` steps (relative wJ-weighted L2 error of
+    u, and kinetic energy)."""
+    cf, cc = coarse_pair(make_case, Nf, Nc)
+    fine = sel.from_case(cf, precision=precision, device=device)
+    ref = sel.from_case(cc, precision=precision, device=device)
+    plain = sel.from_case(cc, precision=precision, device=device)
+    clos = sel.from_case(cc, precision=precision, device=device, closure=blob)
+    sel.coarse_grain(fine, plain)
+    sel.coarse_grain(fine, clos)
+    wJ, _ = ref.geometry()
+    dim = cc.dim
+    J = Judgement([], [], [], [], [], [])
+    for _ in range(nchk):
+        fine.step(every)
+        plain.step(every)
+        clos.step(every)
+        sel.coarse_grain(fine, ref)
+        _, ur = ref.moments()
+        _, up = plain.moments()
+        _, uc = clos.moments()
+        J.times.append(fine.time)
+        J.err_plain.append(_l2(up, ur, wJ))
+        J.err_closure.append(_l2(uc, ur, wJ))
+        J.ke_ref.append(float(ref.reduce()[dim + 1]))
+        J.ke_plain.append(float(plain.reduce()[dim + 1]))
+        J.ke_closure.append(float(clos.reduce()[dim + 1]))
+    return J

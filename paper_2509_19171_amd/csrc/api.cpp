@@ -398,8 +398,8 @@ extern "C" int sel_step_timed(sel_sim *s, int64_t nsteps, double *ms, int64_t *l
     int rc = ops_of(s)->step(s, nsteps);
     s->timing = nullptr;
     if (!rc) rc = sync_check(s);
-    double acc[SEL_NKIND] = {0, 0, 0, 0};
-    int64_t cnt[SEL_NKIND] = {0, 0, 0, 0};
+    double acc[SEL_NKIND] = {};
+    int64_t cnt[SEL_NKIND] = {};
     for (auto &x : ev) {
         float t = 0.f;
         if (!rc && hipEventElapsedTime(&t, x.second.first, x.second.second) != hipSuccess) rc = SEL_EDEVICE;

@@ -178,8 +178,13 @@ struct Impl {
                     s->cur ^= 1;
                     pending = false;
                 }
+                hipEvent_t ev = nullptr;
+                if (int rc = tic(s, 4, ev)) return rc;
                 if (int rc = features(s, s->cl_X, 1)) return rc;
+                if (int rc = toc(s, ev)) return rc;
+                if (int rc = tic(s, 5, ev)) return rc;
                 if (int rc = launch_mlp_infer(s)) return rc;
+                if (int rc = toc(s, ev)) return rc;
                 A.dtau = s->cl_dtau;
             } else {
                 A.dtau = nullptr;

@@ -353,3 +353,28 @@ def random_state(case: Case, seed: int = 7, amp: float = 0.01):
     dr = rng.standard_normal(ng)[case.gid]
     du = rng.standard_normal((ng, case.dim))[case.gid]
     return case.rho + amp * dr, case.u + amp * 0.1 * du
+
+
+# ----------------------------------------------------------------------------
+# Learned-closure initial network
+# ----------------------------------------------------------------------------
+
+CLOSURE_NF, CLOSURE_NH = 6, 64
+
+
+def closure_blob(seed: int, mean, std, dtau_max: float = 100.0, b4: float = -3.0) -> np.ndarray:
+    """Seeded initial parameter blob of the closure network (FP32, layout
+    mean[6], std[6], W1[64][6], b1[64], W2[64][64], b2[64], W3[64][64], b3[64],
+    w4[64], b4, dtau_max): Glorot-uniform weights, zero hidden biases, b4 < 0
+    so that the untrained network starts near dtau = 0."""
+    nf, nh = CLOSURE_NF, CLOSURE_NH
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = [np.asarray(mean, float).reshape(nf), np.asarray(std, float).reshape(nf)]
+    for fo, fi in ((nh, nf), (nh, nh), (nh, nh)):
+        a = math.sqrt(6.0 / (fi + fo))
+        parts.append(rng.uniform(-a, a, size=fo * fi))
+        parts.append(np.zeros(nh))
+    a = math.sqrt(6.0 / (nh + 1))
+    parts.append(rng.uniform(-a, a, size=nh))
+    parts.append(np.array([b4, dtau_max]))
+    return np.concatenate(parts).astype(np.float32)

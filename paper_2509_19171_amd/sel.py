@@ -240,11 +240,11 @@ class Sim:
     def step_timed(self, n):
         """Run n steps with HIP events around every launch; returns
         {kind: (total ms, launches)} for the kernel kinds of sel_step_timed."""
-        ms = np.zeros(4)
-        cnt = np.zeros(4, dtype=np.int64)
+        ms = np.zeros(6)
+        cnt = np.zeros(6, dtype=np.int64)
         _check(self._lib.sel_step_timed(self._h, int(n), _ptr(ms), _ptr(cnt)))
-        names = ["stage1", "stage23", "assembly", "filter"]
-        return {names[k]: (float(ms[k]), int(cnt[k])) for k in range(4)}
+        names = ["stage1", "stage23", "assembly", "filter", "features", "network"]
+        return {names[k]: (float(ms[k]), int(cnt[k])) for k in range(6)}
 
     def sync(self):
         _check(self._lib.sel_sync(self._h))
