@@ -144,21 +144,76 @@ __device__ __forceinline__ void collide_node(T (&v)[Q], T rho0, T omega, T dt, c
     const T uF = u0 * F0 + u1 * F1 + u2 * F2;
     const T c1 = T(3), c2 = T(4.5), c3 = T(1.5);  // 1/cs2, 1/(2 cs4), 1/(2 cs2)
     const T half_dt = T(0.5) * dt;
-    static_for<0, Q>([&](auto A) {
-        constexpr int a = decltype(A)::value;
-        constexpr int ex = lat_e<DIM, Q>(a, 0), ey = lat_e<DIM, Q>(a, 1), ez = lat_e<DIM, Q>(a, 2);
-        const T t = T(lat_t<DIM, Q>(a));
-        const T eu = T(ex) * u0 + T(ey) * u1 + T(ez) * u2;
-        const T eF = T(ex) * F0 + T(ey) * F1 + T(ez) * F2;
-        const T poly = c1 * eu + c2 * eu * eu - c3 * uu;
-        // equilibrium (Eq. geq_s), as a deviation from t rho0 when DEV
-        const T feq = DEV ? t * (m0 + rho * poly) : t * rho * (T(1) + poly);
-        // higher-order force (Eq. f_c): t ((e.u)(e.F)/cs4 - (u.F)/cs2)
-        const T fss = t * (T(9) * eu * eF - T(3) * uF);
-        const T fbeq = feq - half_dt * fss;
-        v[a] = v[a] - omega * (v[a] - fbeq) + dt * fss;
-    });
+    if constexpr (!std::is_same<T, float>::value) {
+        static_for<0, Q>([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            constexpr int ex = lat_e<DIM, Q>(a, 0), ey = lat_e<DIM, Q>(a, 1), ez = lat_e<DIM, Q>(a, 2);
+            const T t = T(lat_t<DIM, Q>(a));
+            const T eu = T(ex) * u0 + T(ey) * u1 + T(ez) * u2;
+            const T eF = T(ex) * F0 + T(ey) * F1 + T(ez) * F2;
+            const T poly = c1 * eu + c2 * eu * eu - c3 * uu;
+            // equilibrium (Eq. geq_s), as a deviation from t rho0 when DEV
+            const T feq = DEV ? t * (m0 + rho * poly) : t * rho * (T(1) + poly);
+            // higher-order force (Eq. f_c): t ((e.u)(e.F)/cs4 - (u.F)/cs2)
+            const T fss = t * (T(9) * eu * eF - T(3) * uF);
+            const T fbeq = feq - half_dt * fss;
+            v[a] = v[a] - omega * (v[a] - fbeq) + dt * fss;
+        });
+    } else {
+        // FP32: the rounded equilibrium does not reproduce rho and j exactly,
+        // and relaxing towards it would leak mass and momentum with a sign
+        // set by the state (a drift over many steps). The non-equilibrium
+        // part n = f - f-bar-eq has zero mass and momentum in exact
+        // arithmetic; its computed moments are sums of small numbers, so
+        // they are accurate, and they are projected out before relaxing:
+        //   n' = n - t (S0 + e.S1 / cs2), f* = f-bar-eq + dt F** + (1 - omega) n + omega (n - n').
+        T base[Q];
+        T S0 = 0, S1x = 0, S1y = 0, S1z = 0;
+        static_for<0, Q>([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            constexpr int ex = lat_e<DIM, Q>(a, 0), ey = lat_e<DIM, Q>(a, 1), ez = lat_e<DIM, Q>(a, 2);
+            const T t = T(lat_t<DIM, Q>(a));
+            const T eu = T(ex) * u0 + T(ey) * u1 + T(ez) * u2;
+            const T eF = T(ex) * F0 + T(ey) * F1 + T(ez) * F2;
+            const T poly = c1 * eu + c2 * eu * eu - c3 * uu;
+            const T feq = DEV ? t * (m0 + rho * poly) : t * rho * (T(1) + poly);
+            const T fss = t * (T(9) * eu * eF - T(3) * uF);
+            const T fbeq = feq - half_dt * fss;
+            const T n = v[a] - fbeq;
+            base[a] = fbeq + dt * fss;
+            v[a] = n;
+            S0 += n;
+            if constexpr (ex != 0) S1x += T(ex) * n;
+            if constexpr (ey != 0) S1y += T(ey) * n;
+            if constexpr (ez != 0) S1z += T(ez) * n;
+        });
+        const T keep = T(1) - omega;
+        static_for<0, Q>([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            constexpr int ex = lat_e<DIM, Q>(a, 0), ey = lat_e<DIM, Q>(a, 1), ez = lat_e<DIM, Q>(a, 2);
+            const T t = T(lat_t<DIM, Q>(a));
+            T es = S0;
+            if constexpr (ex != 0) es += T(3 * ex) * S1x;
+            if constexpr (ey != 0) es += T(3 * ey) * S1y;
+            if constexpr (ez != 0) es += T(3 * ez) * S1z;
+            v[a] = base[a] + (keep * v[a] + omega * (t * es));
+        });
+    }
     rho_out = rho;
+}
+
+// SSPRK stage output ca f0 + cb fk + cc L with ca + cb = 1. FP32 takes the
+// increment form fk + (ca (f0 - fk) + cc L): the weights then sum to one
+// exactly (float(1/3) + float(2/3) exceeds 1 by 3e-8, which would scale the
+// state by that much every step) and only one rounding acts at the size of f.
+// (incr = 0: general weights, as for the single-operator entry point.)
+template <typename T>
+__device__ __forceinline__ T rk_combine(T ca, T cb, T cc, T f0, T fk, T L, int incr)
+{
+    if constexpr (std::is_same<T, float>::value) {
+        if (incr) return fk + (ca * (f0 - fk) + cc * L);
+    }
+    return ca * f0 + cb * fk + cc * L;
 }
 
 // ----------------------------------------------------------- stage kernel --
@@ -179,6 +234,7 @@ struct StageArgs {
     const T *wallu;  // [ntags+1][3]
     int64_t E, nblk, Gi, QGi;
     T dt, omega, rho0, ca, cb, cc;  // output = ca f0 + cb f_k + cc L(f_k)
+    int incr;                       // ca + cb = 1 (time steps): FP32 increment form
     T g[3];
     T fsc[kMaxQ];  // F* per unit density: t_a (e_a . g) / cs2
     int filter;    // M_STAGE1: filter the operand first
@@ -196,6 +252,11 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_stage(StageArgs<T> A)
     // with a software prefetch one chunk ahead. Velocities are processed in
     // chunks of NA planes per LDS barrier.
     constexpr bool ALLQ = (MODE == M_STAGE1 || MODE == M_FILTER);
+    // FP32: line contractions are taken around the node's own value,
+    // sum_q W_q (P_q - x) (+ x for filter rows, which sum to one), so that a
+    // large common level of the populations adds no rounding bias (the
+    // rounded rows of D-hat and F do not sum exactly to 0 and 1)
+    constexpr bool DIF = std::is_same<T, float>::value;
     constexpr int NA = SEL_CHUNK;
     constexpr int NC = (Q + NA - 1) / NA;
     __shared__ T pl[(ALLQ ? 3 : 2) * NA][EPB * NP];
@@ -278,6 +339,7 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_stage(StageArgs<T> A)
             // explicit modal filter (Sec. 2.2.3): (F x F x F) applied one direction at a time
             static_for<0, NC>([&](auto CC) {
                 constexpr int c = decltype(CC)::value;
+                T t1v[NA], t2v[NA];
                 static_for<0, NA>([&](auto UU) {
                     constexpr int u = decltype(UU)::value, a = c * NA + u;
                     if constexpr (a < Q) pl[u][base + p] = fq[a];
@@ -286,9 +348,15 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_stage(StageArgs<T> A)
                 static_for<0, NA>([&](auto UU) {
                     constexpr int u = decltype(UU)::value, a = c * NA + u;
                     if constexpr (a < Q) {
+                        const T x = fq[a];
                         T t1 = 0;
 #pragma unroll
-                        for (int q = 0; q < n1; ++q) t1 += sF[i * n1 + q] * pl[u][rowr + q];
+                        for (int q = 0; q < n1; ++q) {
+                            if constexpr (DIF) t1 += sF[i * n1 + q] * (pl[u][rowr + q] - x);
+                            else t1 += sF[i * n1 + q] * pl[u][rowr + q];
+                        }
+                        if constexpr (DIF) t1 += x;
+                        t1v[u] = t1;
                         pl[NA + u][base + p] = t1;
                     }
                 });
@@ -296,9 +364,15 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_stage(StageArgs<T> A)
                 static_for<0, NA>([&](auto UU) {
                     constexpr int u = decltype(UU)::value, a = c * NA + u;
                     if constexpr (a < Q) {
+                        const T x = t1v[u];
                         T t2 = 0;
 #pragma unroll
-                        for (int q = 0; q < n1; ++q) t2 += sF[j * n1 + q] * pl[NA + u][rows + n1 * q];
+                        for (int q = 0; q < n1; ++q) {
+                            if constexpr (DIF) t2 += sF[j * n1 + q] * (pl[NA + u][rows + n1 * q] - x);
+                            else t2 += sF[j * n1 + q] * pl[NA + u][rows + n1 * q];
+                        }
+                        if constexpr (DIF) t2 += x;
+                        t2v[u] = t2;
                         if constexpr (DIM == 3) pl[2 * NA + u][base + p] = t2;
                         else fq[a] = t2;
                     }
@@ -308,9 +382,14 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_stage(StageArgs<T> A)
                     static_for<0, NA>([&](auto UU) {
                         constexpr int u = decltype(UU)::value, a = c * NA + u;
                         if constexpr (a < Q) {
+                            const T x = t2v[u];
                             T t3 = 0;
 #pragma unroll
-                            for (int q = 0; q < n1; ++q) t3 += sF[k * n1 + q] * pl[2 * NA + u][rowt + n1 * n1 * q];
+                            for (int q = 0; q < n1; ++q) {
+                                if constexpr (DIF) t3 += sF[k * n1 + q] * (pl[2 * NA + u][rowt + n1 * n1 * q] - x);
+                                else t3 += sF[k * n1 + q] * pl[2 * NA + u][rowt + n1 * n1 * q];
+                            }
+                            if constexpr (DIF) t3 += x;
                             fq[a] = t3;
                         }
                     });
@@ -402,13 +481,24 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_stage(StageArgs<T> A)
                 else if constexpr (c & 1) v = roB[u];
                 else v = roA[u];
                 T dr = 0, ds = 0, dtt = 0;
+                if constexpr (DIF) {
 #pragma unroll
-                for (int q = 0; q < n1; ++q) dr += Di[q] * P[rowr + q];
+                    for (int q = 0; q < n1; ++q) dr += Di[q] * (P[rowr + q] - v);
 #pragma unroll
-                for (int q = 0; q < n1; ++q) ds += Dj[q] * P[rows + n1 * q];
-                if constexpr (DIM == 3) {
+                    for (int q = 0; q < n1; ++q) ds += Dj[q] * (P[rows + n1 * q] - v);
+                    if constexpr (DIM == 3) {
 #pragma unroll
-                    for (int q = 0; q < n1; ++q) dtt += Dk[q] * P[rowt + n1 * n1 * q];
+                        for (int q = 0; q < n1; ++q) dtt += Dk[q] * (P[rowt + n1 * n1 * q] - v);
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < n1; ++q) dr += Di[q] * P[rowr + q];
+#pragma unroll
+                    for (int q = 0; q < n1; ++q) ds += Dj[q] * P[rows + n1 * q];
+                    if constexpr (DIM == 3) {
+#pragma unroll
+                        for (int q = 0; q < n1; ++q) dtt += Dk[q] * P[rowt + n1 * n1 * q];
+                    }
                 }
                 // c_m = sum_k e_k G_mk
                 T cr = 0, cs = 0, ct = 0;
@@ -462,7 +552,7 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_stage(StageArgs<T> A)
                             if constexpr (MODE == M_STAGE1) f0v = v;
                             else if constexpr (c & 1) f0v = r0B[u];
                             else f0v = r0A[u];
-                            A.out[si.base + (int64_t)a * si.stride] = A.ca * f0v + A.cb * v + A.cc * L;
+                            A.out[si.base + (int64_t)a * si.stride] = rk_combine(A.ca, A.cb, A.cc, f0v, v, L, A.incr);
                         } else {
                             A.rtb[(e * Q + a) * NB + bsl] = rt;
                         }
@@ -487,6 +577,7 @@ struct GroupArgs {
     int64_t ngrp, Gi, QGi;
     int NB;
     T ca, cb, cc;
+    int incr;  // ca + cb = 1 (time steps): FP32 increment form
     T fsc[kMaxQ];
 };
 
@@ -519,7 +610,7 @@ __global__ void __launch_bounds__(256) k_group(GroupArgs<T> A)
         for (int t = MM; t < nm; ++t) s += r[moff(A.gmem[j0 + t])];
         const int64_t ix = si.base + (int64_t)a * si.stride;
         const T L = s * invM + A.fsc[a] * rho;
-        A.out[ix] = A.ca * A.f0[ix] + A.cb * A.fk[ix] + A.cc * L;
+        A.out[ix] = rk_combine(A.ca, A.cb, A.cc, A.f0[ix], A.fk[ix], L, A.incr);
     });
 }
 

@@ -165,6 +165,8 @@ struct Impl {
         const bool filt = s->p.filter_type != SEL_FILTER_NONE;
         StageArgs<T> A = stage_args(s);
         GroupArgs<T> B = group_args(s);
+        A.incr = 1;  // SSPRK weights sum to one
+        B.incr = 1;
         T *F0 = st(s, 2), *FA = st(s, 3);
         bool pending = false;
         for (int64_t n = 0; n < nsteps; ++n) {

@@ -378,3 +378,186 @@ def closure_blob(seed: int, mean, std, dtau_max: float = 100.0, b4: float = -3.0
     parts.append(rng.uniform(-a, a, size=nh))
     parts.append(np.array([b4, dtau_max]))
     return np.concatenate(parts).astype(np.float32)
+
+
+# ----------------------------------------------------------------------------
+# O-grid pipe (turbulent pipe case)
+# ----------------------------------------------------------------------------
+
+def _pos1d(I, nel, N, x_gll, bounds=None):
+    """Parameter of global node index I on a line of nel elements of order N:
+    element e = min(I // N, nel - 1), GLL point i = I - e N inside it; element
+    bounds default to a uniform split of [-1, 1]."""
+    I = np.asarray(I)
+    e = np.minimum(I // N, nel - 1)
+    i = I - e * N
+    if bounds is None:
+        bounds = np.linspace(-1.0, 1.0, nel + 1)
+    lo, hi = bounds[e], bounds[e + 1]
+    return lo + (hi - lo) * (1.0 + x_gll[i]) / 2.0
+
+
+def pipe_radial_bounds(nrad, a, R, h_wall):
+    """Radial element bounds t_0 = 0 < ... < t_nrad = 1 of the shell blocks in
+    geometric progression, the last element (at the wall) of height h_wall at
+    the middle of each block face (shell thickness R - a there)."""
+    last = h_wall / (R - a)
+    if not 0.0 < last < 1.0:
+        raise ValueError("h_wall must be below the shell thickness")
+
+    def total(q):
+        return sum(q ** -k for k in range(nrad)) * last  # elements from the wall inwards
+
+    lo, hi = 1e-3, 1e3
+    for _ in range(200):
+        mid = math.sqrt(lo * hi)
+        if total(mid) > 1.0:
+            lo = mid
+        else:
+            hi = mid
+    q = math.sqrt(lo * hi)
+    sizes = np.array([last * q ** -(nrad - 1 - k) for k in range(nrad)])
+    sizes /= sizes.sum()
+    return np.concatenate([[0.0], np.cumsum(sizes)])
+
+
+def pipe_mesh(N: int, nsq: int = 8, nrad: int = 8, nax: int = 64, R: float = 1.0, L: float = 10.0,
+              a: float = 0.35, h_wall: float = 0.087) -> Mesh:
+    """O-grid pipe of radius R and periodic length L along z.
+
+    Cross-section: a central square [-a, a]^2 of nsq x nsq elements and four
+    shell blocks of nsq (azimuthal) x nrad (radial) elements between the
+    square's sides and the circle. Shell nodes come from the transfinite
+    (Gordon-Hall) blend of the straight inner side and the exact circular
+    arc; radial element bounds grow geometrically so that the wall element is
+    h_wall high. nax elements along z. Wall faces (tag 1, at rest) are the r+
+    faces of the outermost shell elements. Element node order: central
+    elements (x, y, z); shell elements (radial, azimuthal, z), so every
+    Jacobian is positive. Global ids are assigned from integer block
+    coordinates, so shared nodes are identified exactly."""
+    n1 = N + 1
+    xg = gll_points(N)
+    S = nsq * N  # global node intervals along a square side / an arc
+    T = nrad * N
+    tb = pipe_radial_bounds(nrad, a, R, h_wall)
+    # ---- 2D cross-section: element node keys and coordinates
+    keys2d = []   # per 2D element: list of n1*n1 hashable keys, r fastest
+    xy2d = []     # per 2D element: [n1*n1][2]
+    for ey in range(nsq):
+        for ex in range(nsq):
+            I = ex * N + np.arange(n1)[None, :].repeat(n1, 0)
+            J = ey * N + np.arange(n1)[:, None].repeat(n1, 1)
+            I, J = I.reshape(-1), J.reshape(-1)
+            keys2d.append([("c", int(i), int(j)) for i, j in zip(I, J)])
+            xy2d.append(np.stack([a * _pos1d(I, nsq, N, xg), a * _pos1d(J, nsq, N, xg)], -1))
+
+    def shell_key(b, s, t):
+        if t == 0:  # on the square's side, counter-clockwise along block b
+            if b == 0:
+                return ("c", S, s)
+            if b == 1:
+                return ("c", S - s, S)
+            if b == 2:
+                return ("c", 0, S - s)
+            return ("c", s, 0)
+        if s == S:
+            return ("s", (b + 1) % 4, 0, t)
+        return ("s", b, s, t)
+
+    for b in range(4):
+        c, sn = math.cos(b * math.pi / 2), math.sin(b * math.pi / 2)
+        for ea in range(nsq):
+            for er in range(nrad):
+                # local r = radial (index t), local s = azimuthal (index s)
+                tt = er * N + np.arange(n1)[None, :].repeat(n1, 0)
+                ss = ea * N + np.arange(n1)[:, None].repeat(n1, 1)
+                tt, ss = tt.reshape(-1), ss.reshape(-1)
+                keys2d.append([shell_key(b, int(s_), int(t_)) for s_, t_ in zip(ss, tt)])
+                sp = _pos1d(ss, nsq, N, xg)
+                tp = _pos1d(tt, nrad, N, xg, bounds=tb)
+                inner = np.stack([np.full_like(sp, a), a * sp], -1)
+                th = sp * math.pi / 4
+                outer = np.stack([R * np.cos(th), R * np.sin(th)], -1)
+                p = (1.0 - tp)[:, None] * inner + tp[:, None] * outer
+                xy2d.append(np.stack([c * p[:, 0] - sn * p[:, 1], sn * p[:, 0] + c * p[:, 1]], -1))
+    E2 = len(keys2d)
+    ids = {}
+    id2d = np.zeros((E2, n1 * n1), dtype=np.int64)
+    for e, kl in enumerate(keys2d):
+        for q, k in enumerate(kl):
+            id2d[e, q] = ids.setdefault(k, len(ids))
+    n2d = len(ids)
+    xy2d = np.stack(xy2d)
+    # ---- extrude along z (periodic)
+    zb = np.linspace(0.0, L, nax + 1)
+    E = E2 * nax
+    npn = n1 ** 3
+    xyz = np.zeros((E, npn, 3))
+    gid = np.zeros((E, npn), dtype=np.int64)
+    face_tag = np.zeros((E, 6), dtype=np.int32)
+    kz = np.arange(n1)
+    Kglob = (np.arange(nax)[:, None] * N + kz[None, :]) % (nax * N)  # [nax][n1]
+    zpos = zb[:-1, None] + (zb[1:] - zb[:-1])[:, None] * (1.0 + xg[None, :]) / 2.0
+    for ez in range(nax):
+        sl = slice(ez * E2, (ez + 1) * E2)
+        xyz[sl, :, 0] = np.tile(xy2d[:, :, 0], (1, n1))
+        xyz[sl, :, 1] = np.tile(xy2d[:, :, 1], (1, n1))
+        xyz[sl, :, 2] = np.repeat(zpos[ez], n1 * n1)[None, :]
+        gid[sl] = np.tile(id2d, (1, n1)) + n2d * np.repeat(Kglob[ez], n1 * n1)[None, :]
+    shell_outer = np.zeros(E2, dtype=bool)
+    for b in range(4):
+        for ea in range(nsq):
+            shell_outer[nsq * nsq + b * nsq * nrad + ea * nrad + (nrad - 1)] = True
+    face_tag[np.tile(shell_outer, nax), 1] = 1
+    return Mesh(3, N, xyz, gid, face_tag, np.zeros((1, 3)))
+
+
+def pipe_perturbation(xyz, R, L, amp, seed=180, nmodes=16, scale=None):
+    """Divergence-free perturbation u' = curl(phi A), phi = (1 - r^2/R^2)^2
+    (zero with its gradient at the wall, so u' = 0 there), A a sum of seeded
+    Fourier modes periodic in z; scaled so that max |u'| = amp over the given
+    points, or multiplied by ``scale`` when that is given."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x, y, z = xyz[..., 0], xyz[..., 1], xyz[..., 2]
+    r2 = (x * x + y * y) / (R * R)
+    phi = (1.0 - r2) ** 2
+    dphi = np.stack([-4.0 * (1.0 - r2) * x / (R * R), -4.0 * (1.0 - r2) * y / (R * R), np.zeros_like(x)], -1)
+    A = np.zeros(xyz.shape)
+    curlA = np.zeros(xyz.shape)
+    for _ in range(nmodes):
+        k = np.array([rng.integers(1, 5) * math.pi / R * rng.choice([-1, 1]),
+                      rng.integers(1, 5) * math.pi / R * rng.choice([-1, 1]),
+                      rng.integers(1, 5) * 2 * math.pi / L])
+        av = rng.standard_normal(3)
+        ph = rng.uniform(0, 2 * math.pi)
+        arg = xyz @ k + ph
+        A += np.sin(arg)[..., None] * av
+        curlA += np.cos(arg)[..., None] * np.cross(k, av)
+    u = phi[..., None] * curlA + np.cross(dphi, A)
+    if scale is not None:
+        return u * scale
+    m = np.sqrt((u * u).sum(-1)).max()
+    return u * (amp / m if m > 0 else 0.0)
+
+
+def case_pipe(N=7, nsq=8, nrad=8, nax=64, R=1.0, L=10.0, Re_tau=180.0, Ma=0.1, pert=0.05, seed=180,
+              steps=200, filt="exp", cfl=0.5) -> Case:
+    """Turbulent pipe flow: O-grid, FBB wall at rest, body acceleration
+    g = 2 u_tau^2 / R along z, initial u_z = 2 u_b (1 - r^2/R^2) plus a seeded
+    divergence-free perturbation of pert * u_b. u_b = Ma c_s,
+    u_tau = u_b / 14.7 (the bulk-to-friction ratio at Re_tau = 180),
+    nu = u_tau R / Re_tau."""
+    mesh = pipe_mesh(N, nsq, nrad, nax, R, L)
+    ub = Ma * CS
+    utau = ub / 14.7
+    nu = utau * R / Re_tau
+    g = 2.0 * utau * utau / R
+    dt = stable_dt(mesh, cfl)
+    x = mesh.xyz
+    r2 = (x[..., 0] ** 2 + x[..., 1] ** 2) / (R * R)
+    u = np.zeros(x.shape)
+    u[..., 2] = 2.0 * ub * np.maximum(0.0, 1.0 - r2)
+    u += pipe_perturbation(x, R, L, pert * ub, seed=seed)
+    rho = np.ones(x.shape[:2])
+    return Case("pipe", mesh, 27, 1.0, nu, dt, rho, u, steps, g=(0.0, 0.0, g),
+                meta=dict(R=R, L=L, ub=ub, utau=utau, Re_tau=Re_tau), **_filter_kw(filt, N))

@@ -1,0 +1,112 @@
+"""The O-grid pipe inputs (turbulent pipe case): node numbering, wall
+geometry, radial grading, the divergence-free perturbation, and the oracle's
+view of the mesh (positive Jacobians, volume, a steady rest state)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2509_19171_amd import inputs as I
+
+
+def test_pipe_numbering_and_wall():
+    N, nsq, nrad, nax = 4, 3, 2, 3
+    m = I.pipe_mesh(N, nsq=nsq, nrad=nrad, nax=nax, L=3.0)
+    assert m.E == (nsq * nsq + 4 * nsq * nrad) * nax
+    S, T = nsq * N, nrad * N
+    n2d = (S + 1) ** 2 + 4 * S * T
+    assert m.gid.max() + 1 == n2d * nax * N
+    # copies of a node sit at one position (z modulo the period)
+    x = m.xyz.reshape(-1, 3)
+    g = m.gid.reshape(-1)
+    first = {}
+    for q in range(g.size):
+        first.setdefault(int(g[q]), q)
+    ref = x[[first[int(v)] for v in g]]
+    d = np.abs(x - ref)
+    d[:, 2] = np.minimum(d[:, 2], np.abs(d[:, 2] - 3.0))
+    assert d.max() < 1e-14
+    # nodes at distinct positions have distinct ids
+    key = np.round(np.c_[x[:, :2], np.mod(x[:, 2], 3.0)], 9)
+    _, inv = np.unique(key, axis=0, return_inverse=True)
+    assert inv.max() + 1 == g.max() + 1
+    # wall faces: r+ face of the outermost shell elements, nodes on r = R
+    n1 = N + 1
+    wall = np.argwhere(m.face_tag == 1)
+    assert set(wall[:, 1]) == {1} and len(wall) == 4 * nsq * nax
+    for e in wall[:, 0]:
+        face = m.xyz[e].reshape(n1, n1, n1, 3)[:, :, -1, :]
+        np.testing.assert_allclose(np.hypot(face[..., 0], face[..., 1]), 1.0, rtol=0, atol=1e-14)
+
+
+def test_pipe_radial_grading():
+    tb = I.pipe_radial_bounds(8, 0.35, 1.0, 0.087)
+    assert tb[0] == 0.0 and abs(tb[-1] - 1.0) < 1e-15
+    h = np.diff(tb)
+    np.testing.assert_allclose(h[-1] * 0.65, 0.087, rtol=1e-9)
+    q = h[1:] / h[:-1]
+    np.testing.assert_allclose(q, q[0], rtol=1e-12)  # geometric
+    # first GLL node off the wall: y+ close to 1 at Re_tau = 180 for N = 7
+    x = I.gll_points(7)
+    y1 = 0.087 * (x[1] + 1) / 2
+    assert 0.5 < y1 * 180 < 1.5
+
+
+def test_pipe_perturbation_divergence_free():
+    rng = np.random.Generator(np.random.PCG64(3))
+    r = np.sqrt(rng.uniform(0, 0.95, 200))
+    th = rng.uniform(0, 2 * math.pi, 200)
+    p = np.stack([r * np.cos(th), r * np.sin(th), rng.uniform(0, 10, 200)], -1)
+    h = 1e-5
+    div = np.zeros(200)
+    for k in range(3):
+        dp = np.zeros(3)
+        dp[k] = h
+        up = I.pipe_perturbation(p + dp, 1.0, 10.0, 0.0, scale=1.0)
+        um = I.pipe_perturbation(p - dp, 1.0, 10.0, 0.0, scale=1.0)
+        div += (up[:, k] - um[:, k]) / (2 * h)
+    u = I.pipe_perturbation(p, 1.0, 10.0, 0.0, scale=1.0)
+    # central differences: O(h^2 |k|^3 |u|) truncation, O(eps |u| / h) rounding
+    assert np.abs(div).max() < 1e-6 * np.abs(u).max() * 50
+    # zero at the wall and periodic in z
+    w = np.stack([np.cos(th), np.sin(th), p[:, 2]], -1)
+    both = np.concatenate([w, p, p + [0, 0, 10.0]])
+    ub = I.pipe_perturbation(both, 1.0, 10.0, 1.0)
+    assert np.abs(ub[:200]).max() < 1e-12
+    np.testing.assert_allclose(ub[200:400], ub[400:], atol=1e-12)
+
+
+def test_pipe_case_parameters():
+    c = I.case_pipe(N=3, nsq=2, nrad=2, nax=2)
+    ub = 0.1 / math.sqrt(3)
+    ut = ub / 14.7
+    assert abs(c.meta["utau"] - ut) < 1e-15
+    assert abs(c.nu - ut / 180) < 1e-18
+    assert abs(c.g[2] - 2 * ut * ut) < 1e-18
+    assert c.Q == 27 and c.filter == "exp"
+    # u_z at the wall is zero, maximum near 2 u_b on the axis
+    r = np.hypot(c.xyz[..., 0], c.xyz[..., 1])
+    assert np.abs(c.u[r > 1 - 1e-12]).max() < 1e-12
+    assert abs(c.u[..., 2].max() - 2 * ub) < 0.06 * ub
+
+
+@pytest.mark.parametrize("N", [3, 5, 7])
+def test_pipe_geometry_oracle(oracle_mod, N):
+    """Positive Jacobians; the volume converges to pi R^2 L (circle exact at nodes)."""
+    m = I.pipe_mesh(N, nsq=2, nrad=2, nax=1, L=1.0)
+    s = oracle_mod.OracleSim(3, N, m.xyz, m.gid, m.face_tag, m.wall_u, 27, 1.0, 1e-3, 1e-3)
+    wJ, _, J = s.geometry()
+    assert J.min() > 0
+    err = abs(wJ.sum() - math.pi) / math.pi
+    assert err < {3: 2e-3, 5: 2e-5, 7: 1e-7}[N], err
+
+
+def test_pipe_rest_state_steady(oracle_mod):
+    m = I.pipe_mesh(3, nsq=2, nrad=2, nax=2, L=2.0)
+    s = oracle_mod.OracleSim(3, 3, m.xyz, m.gid, m.face_tag, m.wall_u, 27, 1.0, 1e-3, 0.01, filter="exp",
+                             filter_kc=2, filter_amp=36.0, filter_order=16.0)
+    rho, u = I.rest_fields(m.xyz)
+    s.init(rho, u)
+    f0 = s.get_f()
+    s.step(5)
+    assert np.abs(s.get_f() - f0).max() < 1e-14
