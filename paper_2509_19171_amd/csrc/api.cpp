@@ -41,7 +41,7 @@ constexpr size_t kAlign = 256;
 struct Plan {
     size_t total = 0;
     size_t tabD, tabF, tabW, geoD, geoW, pcode, bpos, xyz, wJ, J, Gm, invw, invMb, bmap, bown, goff, gmem, ftag,
-        wallu, f[4], rtb, rhoc, io, red, flag, cl_params = 0, cl_X = 0, cl_dtau = 0;
+        wallu, f[4], rtb, rhoc, io, red, flag, posmap, hidx, cl_params = 0, cl_X = 0, cl_dtau = 0;
     int nred = 0;
     bool closure = false;
 };
@@ -127,7 +127,9 @@ Plan make_plan(const sel_mesh *m, const sel_params *p)
     L.wallu = carve(c, ts * 3 * (size_t)(m->ntags + 1));
     const int64_t nstate = (int64_t)p->Q * (E * m->nint + (m->ngrp + 63) / 64 * 64);
     for (int i = 0; i < 4; ++i) L.f[i] = carve(c, ts * (size_t)nstate);
-    L.rtb = carve(c, ts * (size_t)(p->Q * E * m->nbe));
+    L.rtb = carve(c, ts * (size_t)p->Q * (size_t)m->plane);
+    L.posmap = carve(c, 4 * (size_t)(E * m->nbe));
+    L.hidx = carve(c, 4 * (size_t)(m->ngrp + 1));
     L.rhoc = carve(c, ts * (size_t)Gtot);
     L.io = carve(c, 8 * (size_t)(E * np * (m->dim + 1)));
     int64_t nred = (E * np + 255) / 256;
@@ -303,6 +305,11 @@ extern "C" int sel_init(const sel_mesh *m, const sel_params *p, const double *rh
     s->wallu = b + L.wallu;
     for (int i = 0; i < 4; ++i) s->f[i] = b + L.f[i];
     s->rtb = b + L.rtb;
+    s->posmap = reinterpret_cast<int32_t *>(b + L.posmap);
+    s->hidx = reinterpret_cast<int32_t *>(b + L.hidx);
+    s->plane = m->plane;
+    s->ngp = m->ngp;
+    s->nmp = m->nmp;
     s->rhoc = b + L.rhoc;
     s->io = reinterpret_cast<double *>(b + L.io);
     s->red = reinterpret_cast<double *>(b + L.red);
@@ -338,6 +345,8 @@ extern "C" int sel_init(const sel_mesh *m, const sel_params *p, const double *rh
     UP(s->goff, m->goff.data(), 4 * m->goff.size());
     UP(s->gmem, m->gmem.data(), 4 * m->gmem.size());
     UP(s->ftag, m->ftag.data(), 4 * m->ftag.size());
+    UP(s->posmap, m->posmap.data(), 4 * m->posmap.size());
+    UP(s->hidx, m->hidx.data(), 4 * m->hidx.size());
     UP(s->io, rho, 8 * nl);
     UP(s->io + nl, u, 8 * nl * m->dim);
 #undef UP

@@ -226,7 +226,9 @@ struct StageArgs {
     T *f0out;        // stage 1: post-collision state written here
     T *rhoc;         // density at the collision [Gtot]
     T *out;          // output state (interior nodes; all owned nodes for M_FILTER)
-    T *rtb;          // element contributions of boundary nodes [E][Q][NB]
+    T *rtb;          // element contributions of boundary nodes [Q][plane]
+    const int32_t *posmap;  // [E][NB] contribution slot of each boundary node
+    int64_t plane;
     T *local;        // M_LOCAL: element contributions [Q][E][NP]
     const T *Gm, *invw, *D, *F;
     const int32_t *pcode, *bmap, *ftag;
@@ -259,7 +261,15 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_stage(StageArgs<T> A)
     constexpr bool DIF = std::is_same<T, float>::value;
     constexpr int NA = SEL_CHUNK;
     constexpr int NC = (Q + NA - 1) / NA;
-    __shared__ T pl[(ALLQ ? 3 : 2) * NA][EPB * NP];
+    // whole-element staging (FP32, one element per workgroup): all Q values
+    // of the node are loaded at once (every load in flight together), all Q
+    // planes of the element go to LDS behind one barrier, and the velocities
+    // are then processed without further waits on global memory
+    constexpr bool FULL = DIF && EPB == 1 && MODE != M_FILTER && Q * NP * 4 <= 80 * 1024;
+    constexpr int PL_N = (ALLQ ? 3 : 2) * NA * EPB * NP;
+    constexpr int LDS_N = FULL ? (ALLQ ? (Q * NP > PL_N ? Q * NP : PL_N) : Q * NP) : PL_N;
+    __shared__ T lds[LDS_N];
+    T(*pl)[EPB * NP] = reinterpret_cast<T(*)[EPB * NP]>(lds);
     __shared__ T sF[ALLQ ? n1 * n1 : 1];
 
     const int tid = threadIdx.x;
@@ -297,17 +307,22 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_stage(StageArgs<T> A)
             si = sidx_group(g, Q, A.QGi);
         }
     }
+    int32_t slot = 0;  // contribution slot of a boundary node
+    if constexpr (MODE != M_LOCAL && MODE != M_FILTER) {
+        if (valid && !inner) slot = A.posmap[e * NB + bsl];
+    }
     const int base = le * NP;
     const int rowr = base + n1 * j + n1 * n1 * k;  // + c       (r line)
     const int rows = base + i + n1 * n1 * k;       // + n1 c    (s line)
     const int rowt = base + i + n1 * j;            // + n1^2 c  (t line)
 
-    T fq[ALLQ ? Q : 1];
+    T fq[(ALLQ || FULL) ? Q : 1];
+    T f0q[(FULL && MODE == M_STAGE23) ? Q : 1];
     // prefetch ring: even chunks in (roA, r0A), odd chunks in (roB, r0B)
     T roA[NA] = {}, r0A[NA] = {}, roB[NA] = {}, r0B[NA] = {};
     auto prefetch = [&](auto CC) {
         constexpr int c = decltype(CC)::value;
-        if constexpr (!ALLQ && c < NC) {
+        if constexpr (!ALLQ && !FULL && c < NC) {
             static_for<0, NA>([&](auto UU) {
                 constexpr int u = decltype(UU)::value, a = c * NA + u;
                 if constexpr (a < Q) {
@@ -324,11 +339,17 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_stage(StageArgs<T> A)
             });
         }
     };
-    if constexpr (ALLQ) {
+    if constexpr (ALLQ || FULL) {
         static_for<0, Q>([&](auto AA) {
             constexpr int a = decltype(AA)::value;
             fq[a] = valid ? A.op[si.base + (int64_t)a * si.stride] : T(0);
         });
+        if constexpr (FULL && MODE == M_STAGE23) {
+            static_for<0, Q>([&](auto AA) {
+                constexpr int a = decltype(AA)::value;
+                f0q[a] = (valid && inner) ? A.f0in[si.base + (int64_t)a * si.stride] : T(0);
+            });
+        }
     } else {
         prefetch(std::integral_constant<int, 0>{});
     }
@@ -457,110 +478,132 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_stage(StageArgs<T> A)
         }
     }
 
-    // streaming operator per velocity (Sec. 2.2): rt = -wJ e . grad f (+ wall flux)
-    static_for<0, NC>([&](auto CC) {
-        constexpr int c = decltype(CC)::value;
-        prefetch(std::integral_constant<int, c + 1>{});
-        constexpr int pb = (c & 1) * NA;  // double-buffered plane set
-        static_for<0, NA>([&](auto UU) {
-            constexpr int u = decltype(UU)::value, a = c * NA + u;
-            if constexpr (a < Q) {
-                if constexpr (ALLQ) pl[pb + u][base + p] = fq[a];
-                else if constexpr (c & 1) pl[pb + u][base + p] = roB[u];
-                else pl[pb + u][base + p] = roA[u];
+    // streaming operator per velocity (Sec. 2.2): rt = -wJ e . grad f (+ wall
+    // flux); P is the velocity's plane in LDS, v and f0v the node's operand
+    // and post-collision values
+    auto velocity = [&](auto AA, const T *P, T v, T f0v) {
+        constexpr int a = decltype(AA)::value;
+        constexpr int ex = lat_e<DIM, Q>(a, 0), ey = lat_e<DIM, Q>(a, 1), ez = lat_e<DIM, Q>(a, 2);
+        T dr = 0, ds = 0, dtt = 0;
+        if constexpr (DIF) {
+#pragma unroll
+            for (int q = 0; q < n1; ++q) dr += Di[q] * (P[rowr + q] - v);
+#pragma unroll
+            for (int q = 0; q < n1; ++q) ds += Dj[q] * (P[rows + n1 * q] - v);
+            if constexpr (DIM == 3) {
+#pragma unroll
+                for (int q = 0; q < n1; ++q) dtt += Dk[q] * (P[rowt + n1 * n1 * q] - v);
             }
+        } else {
+#pragma unroll
+            for (int q = 0; q < n1; ++q) dr += Di[q] * P[rowr + q];
+#pragma unroll
+            for (int q = 0; q < n1; ++q) ds += Dj[q] * P[rows + n1 * q];
+            if constexpr (DIM == 3) {
+#pragma unroll
+                for (int q = 0; q < n1; ++q) dtt += Dk[q] * P[rowt + n1 * n1 * q];
+            }
+        }
+        // c_m = sum_k e_k G_mk
+        T cr = 0, cs = 0, ct = 0;
+        if constexpr (ex != 0) {
+            cr += T(ex) * Gr[0][0];
+            cs += T(ex) * Gr[1][0];
+            if constexpr (DIM == 3) ct += T(ex) * Gr[2][0];
+        }
+        if constexpr (ey != 0) {
+            cr += T(ey) * Gr[0][1];
+            cs += T(ey) * Gr[1][1];
+            if constexpr (DIM == 3) ct += T(ey) * Gr[2][1];
+        }
+        if constexpr (DIM == 3 && ez != 0) {
+            cr += T(ez) * Gr[0][2];
+            cs += T(ez) * Gr[1][2];
+            ct += T(ez) * Gr[2][2];
+        }
+        T rt = -(cr * dr + cs * ds + ct * dtt);
+        if (wcode) {
+            // outward area vector w_s J_s n = +-(w_end)^-1 wJ dr_m/dx on the
+            // face r_m = +-1, from the same metric as the volume term
+            constexpr int b = lat_opp<DIM, Q>(a);
+            const T t = T(lat_t<DIM, Q>(a));
+            T vb;
+            if constexpr (ALLQ || FULL) vb = fq[b];
+            else vb = A.op[si.base + (int64_t)b * si.stride];
+#pragma unroll
+            for (int m = 0; m < DIM; ++m) {
+                const uint32_t code = (wcode >> (8 * m)) & 0xffu;
+                if (code) {
+                    const T sc = ((code & 0x80u) ? T(1) : T(-1)) * T(N * (N + 1)) / T(2);
+                    T ne = T(ex) * Gr[m][0] + T(ey) * Gr[m][1];
+                    if constexpr (DIM == 3) ne += T(ez) * Gr[m][2];
+                    ne *= sc;
+                    if (ne < T(0)) {
+                        const T *ub = A.wallu + 3 * (code & 0x7fu);
+                        const T eub = T(ex) * ub[0] + T(ey) * ub[1] + T(ez) * ub[2];
+                        rt += ne * (v - vb - T(2) * t * A.rho0 * eub * T(3));
+                    }
+                }
+            }
+        }
+        if (valid) {
+            if constexpr (MODE == M_LOCAL) {
+                A.local[((int64_t)a * A.E + e) * NP + p] = rt;
+            } else {
+                if (inner) {
+                    const T L = rt * invw + A.fsc[a] * rho;
+                    A.out[si.base + (int64_t)a * si.stride] = rk_combine(A.ca, A.cb, A.cc, f0v, v, L, A.incr);
+                } else {
+                    A.rtb[(int64_t)a * A.plane + slot] = rt;
+                }
+            }
+        }
+    };
+
+    if constexpr (FULL) {
+        // the filter passes of the first stage used the same LDS
+        if constexpr (ALLQ) __syncthreads();
+        static_for<0, Q>([&](auto AA) {
+            constexpr int a = decltype(AA)::value;
+            pl[a][p] = fq[a];
         });
         __syncthreads();
-        static_for<0, NA>([&](auto UU) {
-            constexpr int u = decltype(UU)::value, a = c * NA + u;
-            if constexpr (a < Q) {
-                constexpr int ex = lat_e<DIM, Q>(a, 0), ey = lat_e<DIM, Q>(a, 1), ez = lat_e<DIM, Q>(a, 2);
-                const T *P = pl[pb + u];
-                T v;
-                if constexpr (ALLQ) v = fq[a];
-                else if constexpr (c & 1) v = roB[u];
-                else v = roA[u];
-                T dr = 0, ds = 0, dtt = 0;
-                if constexpr (DIF) {
-#pragma unroll
-                    for (int q = 0; q < n1; ++q) dr += Di[q] * (P[rowr + q] - v);
-#pragma unroll
-                    for (int q = 0; q < n1; ++q) ds += Dj[q] * (P[rows + n1 * q] - v);
-                    if constexpr (DIM == 3) {
-#pragma unroll
-                        for (int q = 0; q < n1; ++q) dtt += Dk[q] * (P[rowt + n1 * n1 * q] - v);
-                    }
-                } else {
-#pragma unroll
-                    for (int q = 0; q < n1; ++q) dr += Di[q] * P[rowr + q];
-#pragma unroll
-                    for (int q = 0; q < n1; ++q) ds += Dj[q] * P[rows + n1 * q];
-                    if constexpr (DIM == 3) {
-#pragma unroll
-                        for (int q = 0; q < n1; ++q) dtt += Dk[q] * P[rowt + n1 * n1 * q];
-                    }
-                }
-                // c_m = sum_k e_k G_mk
-                T cr = 0, cs = 0, ct = 0;
-                if constexpr (ex != 0) {
-                    cr += T(ex) * Gr[0][0];
-                    cs += T(ex) * Gr[1][0];
-                    if constexpr (DIM == 3) ct += T(ex) * Gr[2][0];
-                }
-                if constexpr (ey != 0) {
-                    cr += T(ey) * Gr[0][1];
-                    cs += T(ey) * Gr[1][1];
-                    if constexpr (DIM == 3) ct += T(ey) * Gr[2][1];
-                }
-                if constexpr (DIM == 3 && ez != 0) {
-                    cr += T(ez) * Gr[0][2];
-                    cs += T(ez) * Gr[1][2];
-                    ct += T(ez) * Gr[2][2];
-                }
-                T rt = -(cr * dr + cs * ds + ct * dtt);
-                if (wcode) {
-                    // outward area vector w_s J_s n = +-(w_end)^-1 wJ dr_m/dx on the
-                    // face r_m = +-1, from the same metric as the volume term
-                    constexpr int b = lat_opp<DIM, Q>(a);
-                    const T t = T(lat_t<DIM, Q>(a));
-                    T vb;
-                    if constexpr (ALLQ) vb = fq[b];
-                    else vb = A.op[si.base + (int64_t)b * si.stride];
-#pragma unroll
-                    for (int m = 0; m < DIM; ++m) {
-                        const uint32_t code = (wcode >> (8 * m)) & 0xffu;
-                        if (code) {
-                            const T sc = ((code & 0x80u) ? T(1) : T(-1)) * T(N * (N + 1)) / T(2);
-                            T ne = T(ex) * Gr[m][0] + T(ey) * Gr[m][1];
-                            if constexpr (DIM == 3) ne += T(ez) * Gr[m][2];
-                            ne *= sc;
-                            if (ne < T(0)) {
-                                const T *ub = A.wallu + 3 * (code & 0x7fu);
-                                const T eub = T(ex) * ub[0] + T(ey) * ub[1] + T(ez) * ub[2];
-                                rt += ne * (v - vb - T(2) * t * A.rho0 * eub * T(3));
-                            }
-                        }
-                    }
-                }
-                if (valid) {
-                    if constexpr (MODE == M_LOCAL) {
-                        A.local[((int64_t)a * A.E + e) * NP + p] = rt;
-                    } else {
-                        if (inner) {
-                            const T L = rt * invw + A.fsc[a] * rho;
-                            T f0v;
-                            if constexpr (MODE == M_STAGE1) f0v = v;
-                            else if constexpr (c & 1) f0v = r0B[u];
-                            else f0v = r0A[u];
-                            A.out[si.base + (int64_t)a * si.stride] = rk_combine(A.ca, A.cb, A.cc, f0v, v, L, A.incr);
-                        } else {
-                            A.rtb[(e * Q + a) * NB + bsl] = rt;
-                        }
-                    }
-                }
-            }
+        static_for<0, Q>([&](auto AA) {
+            constexpr int a = decltype(AA)::value;
+            T f0v;
+            if constexpr (MODE == M_STAGE23) f0v = f0q[a];
+            else f0v = fq[a];
+            velocity(AA, pl[a], fq[a], f0v);
         });
-    });
+    } else {
+        static_for<0, NC>([&](auto CC) {
+            constexpr int c = decltype(CC)::value;
+            prefetch(std::integral_constant<int, c + 1>{});
+            constexpr int pb = (c & 1) * NA;  // double-buffered plane set
+            static_for<0, NA>([&](auto UU) {
+                constexpr int u = decltype(UU)::value, a = c * NA + u;
+                if constexpr (a < Q) {
+                    if constexpr (ALLQ) pl[pb + u][base + p] = fq[a];
+                    else if constexpr (c & 1) pl[pb + u][base + p] = roB[u];
+                    else pl[pb + u][base + p] = roA[u];
+                }
+            });
+            __syncthreads();
+            static_for<0, NA>([&](auto UU) {
+                constexpr int u = decltype(UU)::value, a = c * NA + u;
+                if constexpr (a < Q) {
+                    T v, f0v;
+                    if constexpr (ALLQ) v = fq[a];
+                    else if constexpr (c & 1) v = roB[u];
+                    else v = roA[u];
+                    if constexpr (MODE == M_STAGE1) f0v = v;
+                    else if constexpr (c & 1) f0v = r0B[u];
+                    else f0v = r0A[u];
+                    velocity(std::integral_constant<int, a>{}, pl[pb + u], v, f0v);
+                }
+            });
+        });
+    }
 }
 
 // -------------------------------------------------- boundary-node assembly --
@@ -573,9 +616,8 @@ template <typename T>
 struct GroupArgs {
     const T *rtb, *f0, *fk, *rhoc, *invMb;
     T *out;
-    const int32_t *goff, *gmem;
-    int64_t ngrp, Gi, QGi;
-    int NB;
+    const int32_t *goff, *hidx;
+    int64_t ngrp, Gi, QGi, plane, ngp, nmp;
     T ca, cb, cc;
     int incr;  // ca + cb = 1 (time steps): FP32 increment form
     T fsc[kMaxQ];
@@ -584,33 +626,39 @@ struct GroupArgs {
 template <int Q, typename T>
 __global__ void __launch_bounds__(256) k_group(GroupArgs<T> A)
 {
-    constexpr int MM = 8;  // member offsets kept in registers (more are re-read)
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= A.ngrp) return;
-    const int j0 = A.goff[g];
-    const int nm = A.goff[g + 1] - j0;
-    // member lb = e NB + b holds its velocity a at (e Q + a) NB + b
-    auto moff = [&](int64_t lb) {
-        const int64_t e = lb / A.NB;
-        return e * (int64_t)Q * A.NB + (lb - e * A.NB);
-    };
-    int64_t mm[MM];
-#pragma unroll
-    for (int t = 0; t < MM; ++t) mm[t] = moff(A.gmem[j0 + (t < nm ? t : 0)]);
+    const int nm = A.goff[g + 1] - A.goff[g];
+    // member rank r wrote plane r (r < 2) at g, extra plane r - 2 at hidx[g]
+    const int64_t h = (nm > 2) ? (int64_t)A.hidx[g] : 0;
     const T invM = A.invMb[g];
     const T rho = A.rhoc[A.Gi + g];
     const SIdx si = sidx_group(g, Q, A.QGi);
+    // every load of the group is issued before its first store (the output
+    // may alias the inputs as far as the compiler knows, which would
+    // otherwise put one memory latency per velocity on the critical path)
+    T sum[Q], v0[Q], vk[Q];
     static_for<0, Q>([&](auto AA) {
         constexpr int a = decltype(AA)::value;
-        const T *r = A.rtb + (int64_t)a * A.NB;
-        T s = 0;
-#pragma unroll
-        for (int t = 0; t < MM; ++t)
-            if (t < nm) s += r[mm[t]];
-        for (int t = MM; t < nm; ++t) s += r[moff(A.gmem[j0 + t])];
+        const T *r = A.rtb + (int64_t)a * A.plane;
         const int64_t ix = si.base + (int64_t)a * si.stride;
-        const T L = s * invM + A.fsc[a] * rho;
-        A.out[ix] = rk_combine(A.ca, A.cb, A.cc, A.f0[ix], A.fk[ix], L, A.incr);
+        sum[a] = r[g];
+        if (nm > 1) sum[a] += r[A.ngp + g];
+        v0[a] = A.f0[ix];
+        vk[a] = A.fk[ix];
+    });
+    for (int t = 2; t < nm; ++t) {
+        const int64_t o = 2 * A.ngp + (t - 2) * A.nmp + h;
+        static_for<0, Q>([&](auto AA) {
+            constexpr int a = decltype(AA)::value;
+            sum[a] += A.rtb[(int64_t)a * A.plane + o];
+        });
+    }
+    static_for<0, Q>([&](auto AA) {
+        constexpr int a = decltype(AA)::value;
+        const int64_t ix = si.base + (int64_t)a * si.stride;
+        const T L = sum[a] * invM + A.fsc[a] * rho;
+        A.out[ix] = rk_combine(A.ca, A.cb, A.cc, v0[a], vk[a], L, A.incr);
     });
 }
 

@@ -61,6 +61,8 @@ struct Impl {
         for (int q = 0; q < 3; ++q) A.g[q] = T(q < DIM ? s->p.accel[q] : 0.0);
         for (int a = 0; a < Q; ++a) A.fsc[a] = T(s->fsc[a]);
         A.rtb = static_cast<T *>(s->rtb);
+        A.posmap = s->posmap;
+        A.plane = s->plane;
         A.rhoc = static_cast<T *>(s->rhoc);
         A.tau = T(s->tau);
         A.dtau = nullptr;
@@ -74,11 +76,13 @@ struct Impl {
         B.rhoc = static_cast<const T *>(s->rhoc);
         B.invMb = static_cast<const T *>(s->invMb);
         B.goff = s->goff;
-        B.gmem = s->gmem;
+        B.hidx = s->hidx;
         B.ngrp = s->ngrp;
         B.Gi = s->Gi;
         B.QGi = (int64_t)Q * s->Gi;
-        B.NB = NB;
+        B.plane = s->plane;
+        B.ngp = s->ngp;
+        B.nmp = s->nmp;
         for (int a = 0; a < Q; ++a) B.fsc[a] = T(s->fsc[a]);
         return B;
     }

@@ -1,6 +1,7 @@
 // Mesh ingest: validation, structural node classes and the shared-node
 // groups of the continuous-Galerkin assembly.
 #include <algorithm>
+#include <climits>
 #include <cstring>
 #include <new>
 #include <numeric>
@@ -166,6 +167,44 @@ extern "C" int sel_mesh_create(int32_t dim, int32_t N, int64_t E, const double *
         }
         m->goff[ngrp] = (int32_t)pos;
         m->unique_nodes = E * (int64_t)m->nint + ngrp;
+
+        // contribution slots (rank planes): the assembly reads consecutive
+        // groups from consecutive addresses
+        m->ngp = (ngrp + 63) / 64 * 64;
+        m->hidx.assign((size_t)ngrp, -1);
+        int64_t nmulti = 0;
+        int maxm = 0;
+        for (int64_t g = 0; g < ngrp; ++g) {
+            const int c = m->goff[g + 1] - m->goff[g];
+            maxm = std::max(maxm, c);
+            if (c > 2) m->hidx[g] = (int32_t)nmulti++;
+        }
+        m->nmp = (nmulti + 63) / 64 * 64;
+        m->maxm = maxm;
+        m->plane = 2 * m->ngp + (maxm > 2 ? (int64_t)(maxm - 2) * m->nmp : 0);
+        if (m->plane > INT32_MAX) {
+            set_error("sel_mesh_create: mesh too large for 32-bit contribution slots");
+            delete m;
+            return SEL_EUNSUPPORTED;
+        }
+        m->posmap.resize(nlb);
+        for (int64_t g = 0; g < ngrp; ++g)
+            for (int r = 0; r < m->goff[g + 1] - m->goff[g]; ++r) {
+                const int32_t lb = m->gmem[m->goff[g] + r];
+                m->posmap[lb] = (int32_t)(r < 2 ? r * m->ngp + g : 2 * m->ngp + (r - 2) * m->nmp + m->hidx[g]);
+            }
+        {  // every slot in range and written by one element-boundary node only
+            std::vector<uint8_t> used((size_t)m->plane, 0);
+            for (int64_t lb = 0; lb < nlb; ++lb) {
+                const int32_t q = m->posmap[lb];
+                if (q < 0 || q >= m->plane || used[q]) {
+                    set_error("sel_mesh_create: internal error in contribution slots");
+                    delete m;
+                    return SEL_EINVAL;
+                }
+                used[q] = 1;
+            }
+        }
     } catch (const std::bad_alloc &) {
         set_error("sel_mesh_create: out of host memory");
         delete m;

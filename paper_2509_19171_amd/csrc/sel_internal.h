@@ -58,6 +58,13 @@ struct sel_mesh {
     std::vector<int32_t> gmem;     // members as e * nbe + b, ascending
     int64_t nwall = 0;
     int64_t unique_nodes = 0;
+    // element-contribution slots: member rank r of group g writes plane r
+    // (r < 2) at index g, or extra plane r - 2 at the group's index among the
+    // groups with more than two members (hidx)
+    int64_t ngp = 0, nmp = 0, plane = 0;  // padded group / multi-group counts, floats per velocity
+    int maxm = 0;
+    std::vector<int32_t> posmap;  // [E][nbe] slot of each element-boundary node
+    std::vector<int32_t> hidx;    // [ngrp] index among groups with > 2 members, or -1
 };
 
 // Device arrays of a simulation, all carved out of one workspace.
@@ -93,9 +100,12 @@ struct sel_sim {
     int32_t *goff = nullptr;   // [ngrp+1]
     int32_t *gmem = nullptr;   // [E*nbe]
     int32_t *ftag = nullptr;   // [E][2 dim]
+    int32_t *posmap = nullptr; // [E][nbe] contribution slot
+    int32_t *hidx = nullptr;   // [ngrp]
+    int64_t plane = 0, ngp = 0, nmp = 0;
     void *wallu = nullptr;     // T [ntags+1][3], row 0 = zero
     void *f[4] = {};           // T [nstate]: state, f0, stage a, stage b
-    void *rtb = nullptr;       // T [E][Q][nbe]
+    void *rtb = nullptr;       // T [Q][plane] element contributions of boundary nodes
     void *rhoc = nullptr;      // T [Gtot]
     double *io = nullptr;      // FP64 [E][np][dim+1] (moments / per-velocity transfers)
     double *red = nullptr;     // FP64 [nred][8] partial sums
