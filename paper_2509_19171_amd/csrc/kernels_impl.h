@@ -245,7 +245,7 @@ struct StageArgs {
 };
 
 template <int DIM, int N, int Q, typename T, bool DEV, int MODE>
-__global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_stage(StageArgs<T> A)
+__global__ void __launch_bounds__((Geo<DIM, N>::BLOCK), (((MODE == M_STAGE23 || MODE == M_STAGE1) && sizeof(T) == 4) ? 4 : 1)) k_stage(StageArgs<T> A)
 {
     using GG = Geo<DIM, N>;
     constexpr int n1 = GG::n1, NP = GG::NP, NI = GG::NI, NB = GG::NB, EPB = GG::EPB;
@@ -266,8 +266,12 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_stage(StageArgs<T> A)
     // planes of the element go to LDS behind one barrier, and the velocities
     // are then processed without further waits on global memory
     constexpr bool FULL = DIF && EPB == 1 && MODE != M_FILTER && Q * NP * 4 <= 80 * 1024;
+    // FP32 filter with all Q planes in LDS (first stage and filter-only launch)
+    constexpr bool FF = DIF && EPB == 1 && ALLQ && Q * NP * 4 <= 80 * 1024;
+    // later stages also stage their results through LDS for coalesced stores
+    constexpr bool STG = FULL && (MODE == M_STAGE23 || MODE == M_STAGE1);
     constexpr int PL_N = (ALLQ ? 3 : 2) * NA * EPB * NP;
-    constexpr int LDS_N = FULL ? (ALLQ ? (Q * NP > PL_N ? Q * NP : PL_N) : Q * NP) : PL_N;
+    constexpr int LDS_N = (FULL || FF) ? (ALLQ ? (Q * NP > PL_N ? Q * NP : PL_N) : Q * NP) : PL_N;
     __shared__ T lds[LDS_N];
     T(*pl)[EPB * NP] = reinterpret_cast<T(*)[EPB * NP]>(lds);
     __shared__ T sF[ALLQ ? n1 * n1 : 1];
@@ -355,7 +359,38 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_stage(StageArgs<T> A)
     }
 
     if constexpr (ALLQ) {
-        if (filt) {
+        if (filt && FF) {
+            // explicit modal filter (Sec. 2.2.3), all velocities per pass: the
+            // node's values go to the Q planes, each pass is computed into
+            // registers and written back (two barriers per pass)
+            static_for<0, Q>([&](auto AA) {
+                constexpr int a = decltype(AA)::value;
+                pl[a][p] = fq[a];
+            });
+            __syncthreads();  // planes and sF visible
+            static_for<0, DIM>([&](auto MM) {
+                constexpr int m = decltype(MM)::value;
+                const int row = (m == 0) ? rowr : (m == 1) ? rows : rowt;
+                constexpr int st = (m == 0) ? 1 : (m == 1) ? n1 : n1 * n1;
+                const int ir = (m == 0) ? i : (m == 1) ? j : k;
+                static_for<0, Q>([&](auto AA) {
+                    constexpr int a = decltype(AA)::value;
+                    const T x = fq[a];
+                    T t = 0;
+#pragma unroll
+                    for (int q = 0; q < n1; ++q) t += sF[ir * n1 + q] * (pl[a][row + st * q] - x);
+                    fq[a] = t + x;
+                });
+                if constexpr (m + 1 < DIM) {
+                    __syncthreads();  // every read of this pass done
+                    static_for<0, Q>([&](auto AA) {
+                        constexpr int a = decltype(AA)::value;
+                        pl[a][p] = fq[a];
+                    });
+                    __syncthreads();
+                }
+            });
+        } else if (filt) {
             __syncthreads();  // sF visible
             // explicit modal filter (Sec. 2.2.3): (F x F x F) applied one direction at a time
             static_for<0, NC>([&](auto CC) {
@@ -528,7 +563,8 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_stage(StageArgs<T> A)
             constexpr int b = lat_opp<DIM, Q>(a);
             const T t = T(lat_t<DIM, Q>(a));
             T vb;
-            if constexpr (ALLQ || FULL) vb = fq[b];
+            if constexpr (STG) vb = pl[b][p];
+            else if constexpr (ALLQ || FULL) vb = fq[b];
             else vb = A.op[si.base + (int64_t)b * si.stride];
 #pragma unroll
             for (int m = 0; m < DIM; ++m) {
@@ -546,7 +582,11 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_stage(StageArgs<T> A)
                 }
             }
         }
-        if (valid) {
+        if constexpr (STG) {
+            // kept in the register of the consumed operand, stored after the loop
+            if (inner) fq[a] = rk_combine(A.ca, A.cb, A.cc, f0v, v, rt * invw + A.fsc[a] * rho, A.incr);
+            else fq[a] = rt;
+        } else if (valid) {
             if constexpr (MODE == M_LOCAL) {
                 A.local[((int64_t)a * A.E + e) * NP + p] = rt;
             } else {
@@ -575,6 +615,37 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_stage(StageArgs<T> A)
             else f0v = fq[a];
             velocity(AA, pl[a], fq[a], f0v);
         });
+        if constexpr (STG) {
+            // results go through LDS in global order: the element's interior
+            // block [Q][NI] is one contiguous run, and the boundary
+            // contributions are written slot by slot in face order
+            __syncthreads();  // every plane read done
+            if (inner) {
+                static_for<0, Q>([&](auto AA) {
+                    constexpr int a = decltype(AA)::value;
+                    lds[a * NI + pc] = fq[a];
+                });
+            } else {
+                static_for<0, Q>([&](auto AA) {
+                    constexpr int a = decltype(AA)::value;
+                    lds[Q * NI + a * NB + bsl] = fq[a];
+                });
+            }
+            __syncthreads();
+            T *dst = A.out + e * (int64_t)Q * NI;
+            if constexpr ((Q * NI) % 4 == 0) {
+                typedef T v4 __attribute__((ext_vector_type(4)));
+                for (int q = tid; q < Q * NI / 4; q += GG::BLOCK)
+                    reinterpret_cast<v4 *>(dst)[q] = reinterpret_cast<const v4 *>(lds)[q];
+            } else {
+                for (int q = tid; q < Q * NI; q += GG::BLOCK) dst[q] = lds[q];
+            }
+            const int32_t *pm = A.posmap + e * NB;
+            for (int q = tid; q < Q * NB; q += GG::BLOCK) {
+                const int a = q / NB, b = q - a * NB;
+                A.rtb[(int64_t)a * A.plane + pm[b]] = lds[Q * NI + q];
+            }
+        }
     } else {
         static_for<0, NC>([&](auto CC) {
             constexpr int c = decltype(CC)::value;
