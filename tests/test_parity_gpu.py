@@ -80,6 +80,23 @@ def _cases_small():
     m1 = I.box_mesh(2, 6, (1, 1), (0, 0), (2 * math.pi, 2 * math.pi), (True, True))
     r1, u1 = I.tgv2d_fields(m1.xyz, 0.05)
     out["single_element_N6"] = I.Case("single", m1, 9, 1.0, 0.01, I.stable_dt(m1), r1, u1, 0)
+    # one element per workgroup in 3D (N >= 5): the FP32 whole-element path,
+    # D3Q19 with FBB walls and a body force, and the largest order (N = 8)
+    def warp5(x):  # periodic in x and z, flat walls at y = 0, 1
+        out = x.copy()
+        out[..., 0] += 0.02 * np.sin(2 * math.pi * x[..., 2] / 1.5)
+        out[..., 1] += 0.02 * np.sin(math.pi * x[..., 1]) * np.sin(2 * math.pi * x[..., 0])
+        out[..., 2] += 0.02 * np.sin(2 * math.pi * x[..., 0])
+        return out
+
+    m5 = I.box_mesh(3, 5, (2, 2, 3), (0, 0, 0), (1, 1, 1.5), (True, False, True), wall_tags={1: (1, 2)},
+                    wall_u=[[0, 0, 0], [0.02, 0, 0.01]], warp=warp5)
+    r5, u5 = I.rest_fields(m5.xyz)
+    c5 = I.Case("box3d_q19_N5", m5, 19, 1.0, 0.01, I.stable_dt(m5), r5, u5, 0, g=(0.0, 0.0, 1e-3),
+                filter="quad", filter_kc=2, filter_amp=0.1)
+    c5.rho, c5.u = I.random_state(c5, seed=8, amp=0.01)
+    out["box3d_q19_walls_N5"] = c5
+    out["tgv3d_q27_N8"] = I.case_tgv3d(nel=2, N=8, Q=27, Re=200.0, steps=0, filt="exp")
     return out
 
 
@@ -130,7 +147,8 @@ def test_operator_parity(name, op, prec, tol):
 
 @pytest.mark.parametrize("name,steps", [("tgv2d_ragged_N5", 200), ("channel_curved_N7", 200),
                                         ("poiseuille_curved_N6", 200), ("tgv3d_q27_N4", 40),
-                                        ("box3d_q19_walls_N3", 60), ("single_element_N6", 100)])
+                                        ("box3d_q19_walls_N3", 60), ("single_element_N6", 100),
+                                        ("box3d_q19_walls_N5", 40), ("tgv3d_q27_N8", 20)])
 def test_step_parity_fp64(name, steps):
     c = CASES[name]
     say(f"steps fp64 {name} x{steps}")
@@ -147,7 +165,8 @@ def test_step_parity_fp64(name, steps):
 
 
 @pytest.mark.parametrize("name,steps", [("tgv2d_ragged_N5", 200), ("channel_curved_N7", 200),
-                                        ("tgv3d_q27_N4", 200), ("box3d_q19_walls_N3", 200)])
+                                        ("tgv3d_q27_N4", 200), ("box3d_q19_walls_N3", 200),
+                                        ("box3d_q19_walls_N5", 200), ("tgv3d_q27_N8", 200)])
 def test_step_parity_fp32dev(name, steps):
     c = CASES[name]
     say(f"steps fp32dev {name} x{steps}")
