@@ -27,6 +27,14 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float softplusf(float z) { return fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))); }
 
+// tanh x = 1 - 2 / (exp(2x) + 1) with the hardware exp2 and reciprocal
+// (absolute error about 1e-7; exp2 overflow gives the limits +-1)
+__device__ __forceinline__ float tanh_fast(float x)
+{
+    const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);  // exp(2x) = 2^(2x / ln 2)
+    return 1.f - 2.f * __builtin_amdgcn_rcpf(e + 1.f);
+}
+
 __device__ __forceinline__ float guard_dtau(float d, float tau, float dmax)
 {
     // fallback to the plain method (0) for non-finite or out-of-range values
@@ -34,10 +42,14 @@ __device__ __forceinline__ float guard_dtau(float d, float tau, float dmax)
 }
 
 // ------------------------------------------------------------ inference --
-// One workgroup of 4 wavefronts; each wavefront runs a tile of 64 rows
+// One workgroup of 4 wavefronts; each wavefront runs a tile of RW = 32 rows
 // through 6 -> 64 -> 64 -> 64 -> 1 with v_mfma_f32_16x16x4f32 for the three
-// hidden layers (A = activations, B = W^T, 4 x 4 output tiles of 16 x 16,
-// activations re-laid out through LDS between layers).
+// hidden layers (A = activations, B = W^T, 2 x 4 output tiles of 16 x 16,
+// activations re-laid out through LDS between layers). 71 KB of LDS, so two
+// workgroups share a CU.
+constexpr int RW = 32;  // rows per wavefront
+constexpr int RT = RW / 16;
+
 __global__ void __launch_bounds__(256) k_mlp_infer(const float *__restrict__ P, const float *__restrict__ X,
                                                    int64_t n, float tau, float *__restrict__ zout,
                                                    float *__restrict__ dtau)
@@ -46,7 +58,7 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const float *__restrict__ P, 
     __shared__ float sW2[NH][NH + 1];
     __shared__ float sW3[NH][NH + 1];
     __shared__ float sb1[NH], sb2[NH], sb3[NH], sw4[NH];
-    __shared__ float sH[4][64][NH + 1];
+    __shared__ float sH[4][RW][NH + 1];
     __shared__ float smean[NF], sistd[NF];
     const int tid = threadIdx.x;
     for (int q = tid; q < NH * 8; q += 256) {
@@ -71,40 +83,43 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const float *__restrict__ P, 
     const float b4 = P[OFF_B4], dmax = P[OFF_DMAX];
     const int w = tid / 64, l = tid % 64;
     const int li = l & 15, lk = l >> 4;
-    for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += (int64_t)gridDim.x * 256) {
-        const int64_t r = base + w * 64 + l;
+    for (int64_t base = (int64_t)blockIdx.x * (4 * RW); base < n; base += (int64_t)gridDim.x * (4 * RW)) {
+        // normalised inputs, K padded to 8: lane l fills row l % RW, columns 4 (l / RW) .. +3
+        {
+            const int rr = l % RW, c0 = 4 * (l / RW);
+            const int64_t r = base + w * RW + rr;
 #pragma unroll
-        for (int c = 0; c < 8; ++c) sH[w][l][c] = (c < NF && r < n) ? (X[r * NF + c] - smean[c]) * sistd[c] : 0.f;
+            for (int c = c0; c < c0 + 4; ++c) sH[w][rr][c] = (c < NF && r < n) ? (X[r * NF + c] - smean[c]) * sistd[c] : 0.f;
+        }
         __syncthreads();
-        f4 acc[4][4];
-        // hidden layer 1 (K = 8, zero padded)
+        f4 acc[RT][4];
+        // hidden layer 1 (K = 8)
 #pragma unroll
-        for (int ti = 0; ti < 4; ++ti)
+        for (int ti = 0; ti < RT; ++ti)
 #pragma unroll
             for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
-            float a[4], b[4];
+            float a[RT], b[4];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                a[t] = sH[w][16 * t + li][4 * ks + lk];
-                b[t] = sW1[16 * t + li][4 * ks + lk];
-            }
+            for (int t = 0; t < RT; ++t) a[t] = sH[w][16 * t + li][4 * ks + lk];
 #pragma unroll
-            for (int ti = 0; ti < 4; ++ti)
+            for (int t = 0; t < 4; ++t) b[t] = sW1[16 * t + li][4 * ks + lk];
+#pragma unroll
+            for (int ti = 0; ti < RT; ++ti)
 #pragma unroll
                 for (int tj = 0; tj < 4; ++tj)
                     acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
         }
         __syncthreads();
 #pragma unroll
-        for (int ti = 0; ti < 4; ++ti)
+        for (int ti = 0; ti < RT; ++ti)
 #pragma unroll
             for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int col = 16 * tj + li;
-                    sH[w][16 * ti + 4 * lk + q][col] = tanhf(acc[ti][tj][q] + sb1[col]);
+                    sH[w][16 * ti + 4 * lk + q][col] = tanh_fast(acc[ti][tj][q] + sb1[col]);
                 }
         __syncthreads();
         // hidden layers 2 and 3 (K = 64)
@@ -113,41 +128,46 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const float *__restrict__ P, 
             const float(*Wl)[NH + 1] = layer == 0 ? sW2 : sW3;
             const float *bl = layer == 0 ? sb2 : sb3;
 #pragma unroll
-            for (int ti = 0; ti < 4; ++ti)
+            for (int ti = 0; ti < RT; ++ti)
 #pragma unroll
                 for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = f4{0.f, 0.f, 0.f, 0.f};
             for (int ks = 0; ks < NH / 4; ++ks) {
-                float a[4], b[4];
+                float a[RT], b[4];
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    a[t] = sH[w][16 * t + li][4 * ks + lk];
-                    b[t] = Wl[16 * t + li][4 * ks + lk];
-                }
+                for (int t = 0; t < RT; ++t) a[t] = sH[w][16 * t + li][4 * ks + lk];
 #pragma unroll
-                for (int ti = 0; ti < 4; ++ti)
+                for (int t = 0; t < 4; ++t) b[t] = Wl[16 * t + li][4 * ks + lk];
+#pragma unroll
+                for (int ti = 0; ti < RT; ++ti)
 #pragma unroll
                     for (int tj = 0; tj < 4; ++tj)
                         acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
             }
             __syncthreads();
 #pragma unroll
-            for (int ti = 0; ti < 4; ++ti)
+            for (int ti = 0; ti < RT; ++ti)
 #pragma unroll
                 for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const int col = 16 * tj + li;
-                        sH[w][16 * ti + 4 * lk + q][col] = tanhf(acc[ti][tj][q] + bl[col]);
+                        sH[w][16 * ti + 4 * lk + q][col] = tanh_fast(acc[ti][tj][q] + bl[col]);
                     }
             __syncthreads();
         }
-        // output layer
-        float z = b4;
+        // output layer: two lanes per row, halves of the 64 products
+        {
+            const int rr = l % RW, h = l / RW;
+            float z = 0.f;
 #pragma unroll 8
-        for (int c = 0; c < NH; ++c) z += sH[w][l][c] * sw4[c];
-        if (r < n) {
-            if (zout) zout[r] = z;
-            if (dtau) dtau[r] = guard_dtau(tau * softplusf(z), tau, dmax);
+            for (int c = 32 * h; c < 32 * h + 32; ++c) z += sH[w][rr][c] * sw4[c];
+            z += __shfl_xor(z, 32);
+            z += b4;
+            const int64_t r = base + w * RW + rr;
+            if (h == 0 && r < n) {
+                if (zout) zout[r] = z;
+                if (dtau) dtau[r] = guard_dtau(tau * softplusf(z), tau, dmax);
+            }
         }
         __syncthreads();
     }
@@ -550,8 +570,8 @@ int check_pair(const sel_sim *f, const sel_sim *c)
 int launch_mlp_infer(sel_sim *s)
 {
     const int64_t n = s->Gtot;
-    int64_t nb = (n + 255) / 256;
-    if (nb > 2048) nb = 2048;
+    int64_t nb = (n + 4 * RW - 1) / (4 * RW);
+    if (nb > 4096) nb = 4096;
     hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)nb), dim3(256), 0, s->stream, s->cl_params, s->cl_X, n,
                        float(s->tau), nullptr, s->cl_dtau);
     hipError_t err = hipGetLastError();
@@ -601,7 +621,7 @@ extern "C" int sel_closure_features(sel_sim *s, float *d_X)
         set_error("sel_closure_features: null argument");
         return SEL_EINVAL;
     }
-    return sel::find_ops(s->dim, s->N, s->Q, s->prec)->features(s, d_X, 0);
+    return sel::find_ops(s->dim, s->N, s->Q, s->prec)->features(s, d_X, 0, 0);
 }
 
 extern "C" int sel_closure_dtau(sel_sim *s, float *d_dtau)
@@ -614,7 +634,7 @@ extern "C" int sel_closure_dtau(sel_sim *s, float *d_dtau)
         set_error("sel_closure_dtau: no closure attached");
         return SEL_ESTATE;
     }
-    if (int rc = sel::find_ops(s->dim, s->N, s->Q, s->prec)->features(s, s->cl_X, 1)) return rc;
+    if (int rc = sel::find_ops(s->dim, s->N, s->Q, s->prec)->features(s, s->cl_X, 1, 0)) return rc;
     if (int rc = sel::launch_mlp_infer(s)) return rc;
     if (hipMemcpyAsync(d_dtau, s->cl_dtau, sizeof(float) * s->Gtot, hipMemcpyDeviceToDevice, s->stream) != hipSuccess) {
         set_error("sel_closure_dtau: copy failed");
@@ -679,8 +699,8 @@ extern "C" int sel_mlp_forward(const float *d_params, const float *d_X, int64_t 
         return SEL_EINVAL;
     }
     if (n == 0) return SEL_OK;
-    int64_t nb = (n + 255) / 256;
-    if (nb > 2048) nb = 2048;
+    int64_t nb = (n + 4 * sel::RW - 1) / (4 * sel::RW);
+    if (nb > 4096) nb = 4096;
     hipLaunchKernelGGL(sel::k_mlp_infer, dim3((unsigned)nb), dim3(256), 0, static_cast<hipStream_t>(stream), d_params,
                        d_X, n, float(tau), d_z, d_dtau);
     if (hipGetLastError() != hipSuccess) {

@@ -743,7 +743,7 @@ __global__ void __launch_bounds__(256) k_group(GroupArgs<T> A)
 // owner_out: one row per node id (owning copy); else one row per element node.
 template <typename T>
 struct FeatArgs {
-    const T *f, *Gm, *D;
+    const T *f, *Gm, *D, *F;
     const double *wJ;
     const int32_t *pcode, *bmap;
     const uint8_t *bown;
@@ -751,6 +751,7 @@ struct FeatArgs {
     int64_t E, nblk, Gi, QGi;
     T rho0, lam;
     int owner_out;
+    int filter;  // features of the filtered state (the filter is linear, so the moment fields are filtered)
 };
 
 template <int DIM, int N, int Q, typename T, bool DEV>
@@ -758,7 +759,10 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_features(FeatArgs<T> A
 {
     using GG = Geo<DIM, N>;
     constexpr int n1 = GG::n1, NP = GG::NP, NI = GG::NI, NB = GG::NB, EPB = GG::EPB;
-    __shared__ T pl[DIM][EPB * NP];
+    constexpr int NM = 1 + DIM + DIM * (DIM + 1) / 2;  // m0, j, sum e e f
+    constexpr bool DIF = std::is_same<T, float>::value;
+    __shared__ T pl[NM][EPB * NP];
+    __shared__ T sF[n1 * n1];
     const int tid = threadIdx.x;
     const int le = tid / NP;
     const int p = tid - le * NP;
@@ -766,6 +770,8 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_features(FeatArgs<T> A
     if (eb >= A.nblk) return;
     const int64_t e = eb * EPB + le;
     const bool valid = e < A.E;
+    if (A.filter)
+        for (int q = tid; q < n1 * n1; q += GG::BLOCK) sF[q] = A.F[q];
     const int i = p % n1, j = (p / n1) % n1, k = (DIM == 3) ? p / (n1 * n1) : 0;
     const int pc = A.pcode[p];
     const bool inner = pc >= 0;
@@ -785,38 +791,78 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_features(FeatArgs<T> A
             si = sidx_group(g, Q, A.QGi);
         }
     }
-    T m0 = 0, jv[3] = {0, 0, 0};
-    T fq[Q];
+    const int base = le * NP;
+    const int rowr = base + n1 * j + n1 * n1 * k;
+    const int rows = base + i + n1 * n1 * k;
+    const int rowt = base + i + n1 * j;
+    // moment fields of the node: m0 = sum f (deviation sum when DEV), j = sum e f,
+    // P = sum e e f (deviation part when DEV: the full value adds rho0 cs^2 I)
+    T M[NM] = {};
     static_for<0, Q>([&](auto AA) {
         constexpr int a = decltype(AA)::value;
-        fq[a] = valid ? A.f[si.base + (int64_t)a * si.stride] : T(0);
-        m0 += fq[a];
-        if constexpr (lat_e<DIM, Q>(a, 0) != 0) jv[0] += T(lat_e<DIM, Q>(a, 0)) * fq[a];
-        if constexpr (lat_e<DIM, Q>(a, 1) != 0) jv[1] += T(lat_e<DIM, Q>(a, 1)) * fq[a];
-        if constexpr (lat_e<DIM, Q>(a, 2) != 0) jv[2] += T(lat_e<DIM, Q>(a, 2)) * fq[a];
+        constexpr int ev[3] = {lat_e<DIM, Q>(a, 0), lat_e<DIM, Q>(a, 1), lat_e<DIM, Q>(a, 2)};
+        const T v = valid ? A.f[si.base + (int64_t)a * si.stride] : T(0);
+        M[0] += v;
+        int q = 1 + DIM;
+#pragma unroll
+        for (int r = 0; r < DIM; ++r) {
+            if (ev[r] != 0) M[1 + r] += T(ev[r]) * v;
+#pragma unroll
+            for (int c = r; c < DIM; ++c) {
+                if (ev[r] != 0 && ev[c] != 0) M[q] += T(ev[r] * ev[c]) * v;
+                ++q;
+            }
+        }
     });
-    const T rho = valid ? (DEV ? A.rho0 + m0 : m0) : T(1);
-    T u[3] = {jv[0] / rho, jv[1] / rho, jv[2] / rho};
-    const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    // non-equilibrium second moment
+    if (A.filter) {
+        // explicit modal filter (Sec. 2.2.3) of the moment fields, one direction per pass
+#pragma unroll
+        for (int c = 0; c < NM; ++c) pl[c][base + p] = M[c];
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) {
+            const int row = (m == 0) ? rowr : (m == 1) ? rows : rowt;
+            const int st = (m == 0) ? 1 : (m == 1) ? n1 : n1 * n1;
+            const int ir = (m == 0) ? i : (m == 1) ? j : k;
+#pragma unroll
+            for (int c = 0; c < NM; ++c) {
+                const T x = M[c];
+                T t = 0;
+#pragma unroll
+                for (int q = 0; q < n1; ++q) {
+                    if constexpr (DIF) t += sF[ir * n1 + q] * (pl[c][row + st * q] - x);
+                    else t += sF[ir * n1 + q] * pl[c][row + st * q];
+                }
+                M[c] = DIF ? t + x : t;
+            }
+            __syncthreads();
+            if (m + 1 < DIM) {
+#pragma unroll
+                for (int c = 0; c < NM; ++c) pl[c][base + p] = M[c];
+                __syncthreads();
+            }
+        }
+    }
+    const T rho = valid ? (DEV ? A.rho0 + M[0] : M[0]) : T(1);
+    T u[3] = {0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) u[c] = M[1 + c] / rho;
+    // non-equilibrium second moment: Pi = sum e e f - rho cs^2 I - rho u u
+    // (the second moment of the lattice equilibrium is exactly rho cs^2 I + rho u u)
     T Pi[3][3] = {};
-    static_for<0, Q>([&](auto AA) {
-        constexpr int a = decltype(AA)::value;
-        constexpr int ex = lat_e<DIM, Q>(a, 0), ey = lat_e<DIM, Q>(a, 1), ez = lat_e<DIM, Q>(a, 2);
-        const T t = T(lat_t<DIM, Q>(a));
-        const T eu = T(ex) * u[0] + T(ey) * u[1] + T(ez) * u[2];
-        const T poly = T(3) * eu + T(4.5) * eu * eu - T(1.5) * uu;
-        const T feq = DEV ? t * (m0 + rho * poly) : t * rho * (T(1) + poly);
-        const T d = fq[a] - feq;
-        const int ev[3] = {ex, ey, ez};
+    {
+        int q = 1 + DIM;
 #pragma unroll
         for (int r = 0; r < DIM; ++r)
 #pragma unroll
-            for (int c = 0; c < DIM; ++c)
-                if (ev[r] != 0 && ev[c] != 0) Pi[r][c] += T(ev[r] * ev[c]) * d;
-    });
+            for (int c = r; c < DIM; ++c) {
+                T v = M[q++] - rho * u[r] * u[c];
+                if (r == c) v -= (DEV ? M[0] : rho) * T(1.0 / 3.0);
+                Pi[r][c] = Pi[c][r] = v;
+            }
+    }
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) pl[c][le * NP + p] = u[c];
+    for (int c = 0; c < DIM; ++c) pl[c][base + p] = u[c];
     __syncthreads();
     if (!valid) return;
     const int idx[3] = {i, j, k};
@@ -824,7 +870,7 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_features(FeatArgs<T> A
     T du[3][3] = {};  // du[c][m] = du_c / dr_m
 #pragma unroll
     for (int m = 0; m < DIM; ++m) {
-        const int b0 = le * NP + p - idx[m] * str[m];
+        const int b0 = base + p - idx[m] * str[m];
 #pragma unroll
         for (int q = 0; q < n1; ++q) {
             const T dq = A.D[idx[m] * n1 + q];

@@ -175,18 +175,13 @@ struct Impl {
         bool pending = false;
         for (int64_t n = 0; n < nsteps; ++n) {
             if (s->closure_on) {
-                // the closure reads the filtered state: materialise it, then
-                // infer the per-node relaxation-time increments
-                if (pending) {
-                    A.op = st(s, s->cur);
-                    A.out = st(s, s->cur ^ 1);
-                    if (int rc = launch_stage<M_FILTER>(s, A)) return rc;
-                    s->cur ^= 1;
-                    pending = false;
-                }
+                // the closure reads the filtered state: its features come from
+                // the filtered moment fields (the filter itself stays fused
+                // into the first stage); then the network infers the
+                // per-node relaxation-time increments
                 hipEvent_t ev = nullptr;
                 if (int rc = tic(s, 4, ev)) return rc;
-                if (int rc = features(s, s->cl_X, 1)) return rc;
+                if (int rc = features(s, s->cl_X, 1, pending ? 1 : 0)) return rc;
                 if (int rc = toc(s, ev)) return rc;
                 if (int rc = tic(s, 5, ev)) return rc;
                 if (int rc = launch_mlp_infer(s)) return rc;
@@ -334,10 +329,12 @@ struct Impl {
 
     // closure features of the current state: one row per node id
     // (owner_out = 1) or per element node
-    static int features(sel_sim *s, float *X, int owner_out)
+    static int features(sel_sim *s, float *X, int owner_out, int filter)
     {
         FeatArgs<T> F{};
         F.f = st(s, s->cur);
+        F.F = static_cast<const T *>(s->tabF);
+        F.filter = filter;
         F.Gm = static_cast<const T *>(s->Gm);
         F.D = static_cast<const T *>(s->tabD);
         F.wJ = s->wJ;

@@ -15,7 +15,7 @@ struct Ops {
     int (*scatter)(sel_sim *, int, const double *, void *, bool);
     int (*gather)(sel_sim *, int, const void *, double *, bool);
     int (*apply)(sel_sim *, int, void *, void *, void *);
-    int (*features)(sel_sim *, float *, int);
+    int (*features)(sel_sim *, float *, int owner_out, int filter);
 };
 
 // learned-closure inference on the simulation's feature rows (closure.hip)
