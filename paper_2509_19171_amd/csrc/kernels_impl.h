@@ -266,8 +266,11 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK), (((MODE == M_STAGE23 || 
     // planes of the element go to LDS behind one barrier, and the velocities
     // are then processed without further waits on global memory
     constexpr bool FULL = DIF && EPB == 1 && MODE != M_FILTER && Q * NP * 4 <= 80 * 1024;
-    // FP32 filter with all Q planes in LDS (first stage and filter-only launch)
-    constexpr bool FF = DIF && EPB == 1 && ALLQ && Q * NP * 4 <= 80 * 1024;
+    // FP32 filter with all Q planes in LDS (first stage and filter-only
+    // launch); FP64 uses it for the filter-only launch (110 KB of LDS at
+    // N = 7, Q = 27: one workgroup per CU, which costs the stages more than
+    // the chunked passes)
+    constexpr bool FF = EPB == 1 && ALLQ && (DIF ? Q * NP * 4 <= 80 * 1024 : (MODE == M_FILTER && Q * NP * 8 <= 120 * 1024));
     // later stages also stage their results through LDS for coalesced stores
     constexpr bool STG = FULL && (MODE == M_STAGE23 || MODE == M_STAGE1);
     constexpr int PL_N = (ALLQ ? 3 : 2) * NA * EPB * NP;
