@@ -46,7 +46,10 @@ __device__ __forceinline__ float guard_dtau(float d, float tau, float dmax)
 // through 6 -> 64 -> 64 -> 64 -> 1 with v_mfma_f32_16x16x4f32 for the three
 // hidden layers (A = activations, B = W^T, 2 x 4 output tiles of 16 x 16,
 // activations re-laid out through LDS between layers). 71 KB of LDS, so two
-// workgroups share a CU.
+// workgroups share a CU. Each wavefront's activation buffer is its own and a
+// wavefront's LDS operations complete in order, so inside the row loop only
+// compiler scheduling barriers separate the layers: the four wavefronts of a
+// workgroup run independently.
 constexpr int RW = 32;  // rows per wavefront
 constexpr int RT = RW / 16;
 
@@ -91,7 +94,7 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const float *__restrict__ P, 
 #pragma unroll
             for (int c = c0; c < c0 + 4; ++c) sH[w][rr][c] = (c < NF && r < n) ? (X[r * NF + c] - smean[c]) * sistd[c] : 0.f;
         }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
         f4 acc[RT][4];
         // hidden layer 1 (K = 8)
 #pragma unroll
@@ -111,7 +114,7 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const float *__restrict__ P, 
                 for (int tj = 0; tj < 4; ++tj)
                     acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
         }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int ti = 0; ti < RT; ++ti)
 #pragma unroll
@@ -121,7 +124,7 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const float *__restrict__ P, 
                     const int col = 16 * tj + li;
                     sH[w][16 * ti + 4 * lk + q][col] = tanh_fast(acc[ti][tj][q] + sb1[col]);
                 }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
         // hidden layers 2 and 3 (K = 64)
 #pragma unroll
         for (int layer = 0; layer < 2; ++layer) {
@@ -143,7 +146,7 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const float *__restrict__ P, 
                     for (int tj = 0; tj < 4; ++tj)
                         acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
             }
-            __syncthreads();
+            __builtin_amdgcn_wave_barrier();
 #pragma unroll
             for (int ti = 0; ti < RT; ++ti)
 #pragma unroll
@@ -153,7 +156,7 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const float *__restrict__ P, 
                         const int col = 16 * tj + li;
                         sH[w][16 * ti + 4 * lk + q][col] = tanh_fast(acc[ti][tj][q] + bl[col]);
                     }
-            __syncthreads();
+            __builtin_amdgcn_wave_barrier();
         }
         // output layer: two lanes per row, halves of the 64 products
         {
@@ -169,7 +172,7 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const float *__restrict__ P, 
                 if (dtau) dtau[r] = guard_dtau(tau * softplusf(z), tau, dmax);
             }
         }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
