@@ -216,6 +216,88 @@ __device__ __forceinline__ T rk_combine(T ca, T cb, T cc, T f0, T fk, T L, int i
     return ca * f0 + cb * fk + cc * L;
 }
 
+// Volume part of the streaming operator of velocity a at one node (Sec. 2.2),
+//   rt = -wJ e_a . grad f_a = -sum_m c_m d f_a / d r_m,  c_m = sum_k e_k G_mk,
+// with the reference derivatives from the element's plane P of f_a in LDS
+// (rows of D-hat). FP32 (DIF) takes the line contractions around the node's
+// own value v.
+template <int DIM, int N, int Q, int a, bool DIF, typename T>
+__device__ __forceinline__ T stream_volume(const T *P, T v, const T (&Di)[N + 1], const T (&Dj)[N + 1],
+                                           const T (&Dk)[N + 1], const T (&Gr)[DIM][DIM], int rowr, int rows,
+                                           int rowt)
+{
+    constexpr int n1 = N + 1;
+    constexpr int ex = lat_e<DIM, Q>(a, 0), ey = lat_e<DIM, Q>(a, 1), ez = lat_e<DIM, Q>(a, 2);
+    T dr = 0, ds = 0, dtt = 0;
+    if constexpr (DIF) {
+#pragma unroll
+        for (int q = 0; q < n1; ++q) dr += Di[q] * (P[rowr + q] - v);
+#pragma unroll
+        for (int q = 0; q < n1; ++q) ds += Dj[q] * (P[rows + n1 * q] - v);
+        if constexpr (DIM == 3) {
+#pragma unroll
+            for (int q = 0; q < n1; ++q) dtt += Dk[q] * (P[rowt + n1 * n1 * q] - v);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < n1; ++q) dr += Di[q] * P[rowr + q];
+#pragma unroll
+        for (int q = 0; q < n1; ++q) ds += Dj[q] * P[rows + n1 * q];
+        if constexpr (DIM == 3) {
+#pragma unroll
+            for (int q = 0; q < n1; ++q) dtt += Dk[q] * P[rowt + n1 * n1 * q];
+        }
+    }
+    // c_m = sum_k e_k G_mk
+    T cr = 0, cs = 0, ct = 0;
+    if constexpr (ex != 0) {
+        cr += T(ex) * Gr[0][0];
+        cs += T(ex) * Gr[1][0];
+        if constexpr (DIM == 3) ct += T(ex) * Gr[2][0];
+    }
+    if constexpr (ey != 0) {
+        cr += T(ey) * Gr[0][1];
+        cs += T(ey) * Gr[1][1];
+        if constexpr (DIM == 3) ct += T(ey) * Gr[2][1];
+    }
+    if constexpr (DIM == 3 && ez != 0) {
+        cr += T(ez) * Gr[0][2];
+        cs += T(ez) * Gr[1][2];
+        ct += T(ez) * Gr[2][2];
+    }
+    return -(cr * dr + cs * ds + ct * dtt);
+}
+
+// Flux bounce-back term of velocity a (Sec. 2.2.1) added to rt: on each wall
+// face through the node where e_a is incoming, the population is replaced
+// by the reflected one, f_a - f_b - 2 t_a rho0 (e_a . u_w)/c_s^2 with b the
+// opposite velocity (node values v and vb), times the outward area vector
+// w_s J_s n = +-(w_end)^-1 wJ dr_m/dx of the face r_m = +-1, taken from the
+// same metric as the volume term. wcode: 8 bits per reference direction m,
+// the wall tag (0 = none) and bit 7 for the face r_m = +1.
+template <int DIM, int N, int Q, int a, typename T>
+__device__ __forceinline__ void wall_flux(T &rt, T v, T vb, const T (&Gr)[DIM][DIM], uint32_t wcode,
+                                          const T *wallu, T rho0)
+{
+    constexpr int ex = lat_e<DIM, Q>(a, 0), ey = lat_e<DIM, Q>(a, 1), ez = lat_e<DIM, Q>(a, 2);
+    const T t = T(lat_t<DIM, Q>(a));
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) {
+        const uint32_t code = (wcode >> (8 * m)) & 0xffu;
+        if (code) {
+            const T sc = ((code & 0x80u) ? T(1) : T(-1)) * T(N * (N + 1)) / T(2);
+            T ne = T(ex) * Gr[m][0] + T(ey) * Gr[m][1];
+            if constexpr (DIM == 3) ne += T(ez) * Gr[m][2];
+            ne *= sc;
+            if (ne < T(0)) {
+                const T *ub = wallu + 3 * (code & 0x7fu);
+                const T eub = T(ex) * ub[0] + T(ey) * ub[1] + T(ez) * ub[2];
+                rt += ne * (v - vb - T(2) * t * rho0 * eub * T(3));
+            }
+        }
+    }
+}
+
 // ----------------------------------------------------------- stage kernel --
 enum { M_STAGE1 = 0, M_STAGE23 = 1, M_LOCAL = 2, M_FILTER = 3 };
 
@@ -516,74 +598,18 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK), (((MODE == M_STAGE23 || 
         }
     }
 
-    // streaming operator per velocity (Sec. 2.2): rt = -wJ e . grad f (+ wall
-    // flux); P is the velocity's plane in LDS, v and f0v the node's operand
-    // and post-collision values
+    // streaming operator per velocity (Sec. 2.2): P is the velocity's plane in
+    // LDS, v and f0v the node's operand and post-collision values
     auto velocity = [&](auto AA, const T *P, T v, T f0v) {
         constexpr int a = decltype(AA)::value;
-        constexpr int ex = lat_e<DIM, Q>(a, 0), ey = lat_e<DIM, Q>(a, 1), ez = lat_e<DIM, Q>(a, 2);
-        T dr = 0, ds = 0, dtt = 0;
-        if constexpr (DIF) {
-#pragma unroll
-            for (int q = 0; q < n1; ++q) dr += Di[q] * (P[rowr + q] - v);
-#pragma unroll
-            for (int q = 0; q < n1; ++q) ds += Dj[q] * (P[rows + n1 * q] - v);
-            if constexpr (DIM == 3) {
-#pragma unroll
-                for (int q = 0; q < n1; ++q) dtt += Dk[q] * (P[rowt + n1 * n1 * q] - v);
-            }
-        } else {
-#pragma unroll
-            for (int q = 0; q < n1; ++q) dr += Di[q] * P[rowr + q];
-#pragma unroll
-            for (int q = 0; q < n1; ++q) ds += Dj[q] * P[rows + n1 * q];
-            if constexpr (DIM == 3) {
-#pragma unroll
-                for (int q = 0; q < n1; ++q) dtt += Dk[q] * P[rowt + n1 * n1 * q];
-            }
-        }
-        // c_m = sum_k e_k G_mk
-        T cr = 0, cs = 0, ct = 0;
-        if constexpr (ex != 0) {
-            cr += T(ex) * Gr[0][0];
-            cs += T(ex) * Gr[1][0];
-            if constexpr (DIM == 3) ct += T(ex) * Gr[2][0];
-        }
-        if constexpr (ey != 0) {
-            cr += T(ey) * Gr[0][1];
-            cs += T(ey) * Gr[1][1];
-            if constexpr (DIM == 3) ct += T(ey) * Gr[2][1];
-        }
-        if constexpr (DIM == 3 && ez != 0) {
-            cr += T(ez) * Gr[0][2];
-            cs += T(ez) * Gr[1][2];
-            ct += T(ez) * Gr[2][2];
-        }
-        T rt = -(cr * dr + cs * ds + ct * dtt);
+        T rt = stream_volume<DIM, N, Q, a, DIF>(P, v, Di, Dj, Dk, Gr, rowr, rows, rowt);
         if (wcode) {
-            // outward area vector w_s J_s n = +-(w_end)^-1 wJ dr_m/dx on the
-            // face r_m = +-1, from the same metric as the volume term
             constexpr int b = lat_opp<DIM, Q>(a);
-            const T t = T(lat_t<DIM, Q>(a));
             T vb;
             if constexpr (STG) vb = pl[b][p];
             else if constexpr (ALLQ || FULL) vb = fq[b];
             else vb = A.op[si.base + (int64_t)b * si.stride];
-#pragma unroll
-            for (int m = 0; m < DIM; ++m) {
-                const uint32_t code = (wcode >> (8 * m)) & 0xffu;
-                if (code) {
-                    const T sc = ((code & 0x80u) ? T(1) : T(-1)) * T(N * (N + 1)) / T(2);
-                    T ne = T(ex) * Gr[m][0] + T(ey) * Gr[m][1];
-                    if constexpr (DIM == 3) ne += T(ez) * Gr[m][2];
-                    ne *= sc;
-                    if (ne < T(0)) {
-                        const T *ub = A.wallu + 3 * (code & 0x7fu);
-                        const T eub = T(ex) * ub[0] + T(ey) * ub[1] + T(ez) * ub[2];
-                        rt += ne * (v - vb - T(2) * t * A.rho0 * eub * T(3));
-                    }
-                }
-            }
+            wall_flux<DIM, N, Q, a>(rt, v, vb, Gr, wcode, A.wallu, A.rho0);
         }
         if constexpr (STG) {
             // kept in the register of the consumed operand, stored after the loop

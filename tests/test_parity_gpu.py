@@ -97,6 +97,15 @@ def _cases_small():
     c5.rho, c5.u = I.random_state(c5, seed=8, amp=0.01)
     out["box3d_q19_walls_N5"] = c5
     out["tgv3d_q27_N8"] = I.case_tgv3d(nel=2, N=8, Q=27, Re=200.0, steps=0, filt="exp")
+    # the benchmark order (N = 7) with curved FBB walls, both 3D lattices
+    for Q, nel in ((27, (2, 2, 3)), (19, (3, 2, 2))):
+        m7 = I.box_mesh(3, 7, nel, (0, 0, 0), (1, 1, 1.5), (True, False, True), wall_tags={1: (1, 2)},
+                        wall_u=[[0, 0, 0], [0.02, 0, 0.01]], warp=warp5)
+        r7, u7 = I.rest_fields(m7.xyz)
+        c7 = I.Case(f"box3d_q{Q}_N7", m7, Q, 1.0, 0.01, I.stable_dt(m7), r7, u7, 0, g=(0.0, 0.0, 1e-3),
+                    filter="quad", filter_kc=2, filter_amp=0.1)
+        c7.rho, c7.u = I.random_state(c7, seed=9, amp=0.01)
+        out[f"box3d_q{Q}_walls_N7"] = c7
     return out
 
 
@@ -148,7 +157,8 @@ def test_operator_parity(name, op, prec, tol):
 @pytest.mark.parametrize("name,steps", [("tgv2d_ragged_N5", 200), ("channel_curved_N7", 200),
                                         ("poiseuille_curved_N6", 200), ("tgv3d_q27_N4", 40),
                                         ("box3d_q19_walls_N3", 60), ("single_element_N6", 100),
-                                        ("box3d_q19_walls_N5", 40), ("tgv3d_q27_N8", 20)])
+                                        ("box3d_q19_walls_N5", 40), ("tgv3d_q27_N8", 20),
+                                        ("box3d_q27_walls_N7", 20), ("box3d_q19_walls_N7", 20)])
 def test_step_parity_fp64(name, steps):
     c = CASES[name]
     say(f"steps fp64 {name} x{steps}")
@@ -166,7 +176,8 @@ def test_step_parity_fp64(name, steps):
 
 @pytest.mark.parametrize("name,steps", [("tgv2d_ragged_N5", 200), ("channel_curved_N7", 200),
                                         ("tgv3d_q27_N4", 200), ("box3d_q19_walls_N3", 200),
-                                        ("box3d_q19_walls_N5", 200), ("tgv3d_q27_N8", 200)])
+                                        ("box3d_q19_walls_N5", 200), ("tgv3d_q27_N8", 200),
+                                        ("box3d_q27_walls_N7", 200), ("box3d_q19_walls_N7", 200)])
 def test_step_parity_fp32dev(name, steps):
     c = CASES[name]
     say(f"steps fp32dev {name} x{steps}")
