@@ -84,10 +84,6 @@ int check_params(const sel_mesh *m, const sel_params *p)
         set_error("unknown rk");
         return SEL_EINVAL;
     }
-    if (p->rk == SEL_RK_PRINTED4) {
-        set_error("the printed four-stage form is not built into the device path");
-        return SEL_EUNSUPPORTED;
-    }
     if (p->closure != nullptr && p->closure_len != sel_closure_len()) {
         set_error("closure_len must equal sel_closure_len()");
         return SEL_EINVAL;

@@ -162,6 +162,63 @@ struct Impl {
     // one time step: collide (and filter the previous step's result) ->
     // SSPRK3 streaming with F* and the wall flux; the filter of this step is
     // applied by the next step's first stage, or at the end of the call.
+    // One element pass and its assembly: out = ca f0 + cb fk + cc L(fk).
+    static int stage_pass(sel_sim *s, StageArgs<T> &A, GroupArgs<T> &B, const T *fk, const T *f0, T *out,
+                          double ca, double cb, double cc)
+    {
+        A.op = fk;
+        A.f0in = f0;
+        A.out = out;
+        A.ca = T(ca);
+        A.cb = T(cb);
+        A.cc = T(cc);
+        if (int rc = launch_stage<M_STAGE23>(s, A)) return rc;
+        B.f0 = f0;
+        B.fk = fk;
+        B.out = out;
+        B.ca = T(ca);
+        B.cb = T(cb);
+        B.cc = T(cc);
+        return launch_group(s, B);
+    }
+
+    // The four printed stage formulas of Sec. 2.2.2 with L applied linearly
+    // to their combinations (stage values w1..w3, y the post-collision state):
+    //   w1 = y + dt/3 L(y)
+    //   w2 = w1 - 3dt/4 (L(y) - L(w1))
+    //   w3 = w2 + 2dt/3 (L(y) - L(w1) + L(w2))
+    //   y' = w3 - dt/4 (L(y) - L(w1) + L(w2) - L(w3)).
+    // Each earlier L is eliminated through the stage that defines it, so every
+    // stage is a two-state combination ca f0 + cb fk + cc L(fk) with
+    // ca + cb = 1 (exact in exact arithmetic, also for an affine L):
+    //   w2 = 9/4 y - 5/4 w1 + 3dt/4 L(w1)
+    //   w3 = 8/9 w1 + 1/9 w2 + 2dt/3 L(w2)
+    //   y' = 3/8 w2 + 5/8 w3 + dt/4 L(w3).
+    // Arrays: S holds the state and then y'; F0 holds y and then w3; FA w1;
+    // FB w2.
+    static int printed4(sel_sim *s, StageArgs<T> &A, GroupArgs<T> &B, T *S, T *FB, T *F0, T *FA, bool pending)
+    {
+        const double dt = s->p.dt;
+        A.op = S;
+        A.f0out = F0;
+        A.out = FA;
+        A.ca = T(0);
+        A.cb = T(1);
+        A.cc = T(dt / 3.0);
+        A.filter = pending ? 1 : 0;
+        if (int rc = launch_stage<M_STAGE1>(s, A)) return rc;
+        B.f0 = F0;
+        B.fk = F0;
+        B.out = FA;
+        B.ca = T(0);
+        B.cb = T(1);
+        B.cc = T(dt / 3.0);
+        if (int rc = launch_group(s, B)) return rc;
+        if (int rc = stage_pass(s, A, B, FA, F0, FB, 9.0 / 4.0, -5.0 / 4.0, 0.75 * dt)) return rc;
+        if (int rc = stage_pass(s, A, B, FB, FA, F0, 8.0 / 9.0, 1.0 / 9.0, 2.0 / 3.0 * dt)) return rc;
+        return stage_pass(s, A, B, F0, FB, S, 3.0 / 8.0, 5.0 / 8.0, 0.25 * dt);
+    }
+
     static int step(sel_sim *s, int64_t nsteps)
     {
         if (nsteps <= 0) return SEL_OK;
@@ -191,6 +248,13 @@ struct Impl {
                 A.dtau = nullptr;
             }
             T *S = st(s, s->cur), *FB = st(s, s->cur ^ 1);
+            if (s->p.rk == SEL_RK_PRINTED4) {
+                if (int rc = printed4(s, A, B, S, FB, F0, FA, pending)) return rc;
+                pending = filt;
+                s->time += dt;
+                s->nstep += 1;
+                continue;
+            }
             // stage 1: f1 = f0 + dt L(f0), f0 = collide(filter(f3_prev) or f-bar)
             A.op = S;
             A.f0out = F0;
