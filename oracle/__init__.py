@@ -20,6 +20,7 @@ _lib = None
 
 FILTER_CODES = {None: 0, "none": 0, "quad": 1, "exp": 2}
 RK_CODES = {"ssprk3": 0, "printed4": 1}
+COUPLING_CODES = {"cg": 0, "dg": 1}
 
 
 def build(force: bool = True) -> str:
@@ -45,7 +46,7 @@ def _load():
     I = ctypes.c_int
     I64 = ctypes.c_int64
     lib.oracle_create.restype = P
-    lib.oracle_create.argtypes = [I, I, I64, P, P, P, I, P, I, D, D, D, P, I, I, D, D, I]
+    lib.oracle_create.argtypes = [I, I, I64, P, P, P, I, P, I, D, D, D, P, I, I, D, D, I, I]
     lib.oracle_destroy.argtypes = [P]
     for name in ("oracle_init",):
         getattr(lib, name).argtypes = [P, P, P]
@@ -163,7 +164,7 @@ class OracleSim:
     """One oracle simulation on a mesh (FP64, host memory)."""
 
     def __init__(self, dim, N, xyz, gid, face_tag, wall_u, Q, rho0, nu, dt, g=(0.0, 0.0, 0.0),
-                 filter=None, filter_kc=2, filter_amp=0.0, filter_order=2.0, rk="ssprk3"):
+                 filter=None, filter_kc=2, filter_amp=0.0, filter_order=2.0, rk="ssprk3", coupling="cg"):
         lib = _load()
         self.dim, self.N, self.Q = dim, N, Q
         self.nu, self.dt, self.rho0 = float(nu), float(dt), float(rho0)
@@ -180,7 +181,7 @@ class OracleSim:
         h = lib.oracle_create(dim, N, self.E, _ptr(self._xyz), _ptr(self._gid), _ptr(self._ftag),
                               ntags, _ptr(self._wall_u), Q, rho0, nu, dt, _ptr(gg),
                               FILTER_CODES[filter], int(filter_kc), float(filter_amp),
-                              float(filter_order), RK_CODES[rk])
+                              float(filter_order), RK_CODES[rk], COUPLING_CODES[coupling])
         if not h:
             raise ValueError("oracle_create rejected the mesh or parameters")
         self._h = ctypes.c_void_p(h)
@@ -274,7 +275,7 @@ class OracleSim:
 def from_case(case, **over) -> OracleSim:
     """Oracle simulation for a case of the seeded input generators."""
     kw = dict(g=case.g, filter=case.filter, filter_kc=case.filter_kc, filter_amp=case.filter_amp,
-              filter_order=case.filter_order, rk=case.rk)
+              filter_order=case.filter_order, rk=case.rk, coupling=case.coupling)
     kw.update(over)
     sim = OracleSim(case.dim, case.N, case.xyz, case.gid, case.face_tag, case.wall_u, case.Q,
                     case.rho0, case.nu, case.dt, **kw)

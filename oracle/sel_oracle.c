@@ -43,6 +43,16 @@
  *       F* and the wall flux -> filter -> moments. The stage-0 state of the
  *       streaming is the post-collision f* (Eq. perfect1).
  *   R10 Moments carry no half-force shift: rho u = sum e f-bar (Eq. momentum).
+ *   R11 Discontinuous-Galerkin coupling (the alternative the introduction
+ *       sets the method against, with the flux of the cited DG-LBM work):
+ *       every element keeps its own copy of its face nodes, the mass is the
+ *       element's own lumped wJ (no assembly), and every face that is not a
+ *       wall adds the upwind flux of the velocities entering the element,
+ *       (n.e_a) w_s J_s (f_a - f_a^out) for n.e_a < 0, with f^out the value
+ *       at the coincident node of the element across the face (same node
+ *       id); wall faces keep the FBB term of R5. A face whose nodes repeat an
+ *       id (one element along a periodic direction) is rejected: its
+ *       coincident nodes would be ambiguous.
  *
  * Conventions shared with the public interface (the interface documents
  * them; this file re-states them in its own code):
@@ -302,6 +312,12 @@ typedef struct oracle_sim {
     double *wJ;       /* [E][np] */
     double *G;        /* [E][np][3][3]  wJ dr_m/dx_k */
     double *Mg;       /* [E np] assembled lumped mass, indexed by global id */
+    int dg;           /* coupling: 0 continuous (R4), 1 discontinuous (R11) */
+    int nfn;          /* nodes per face */
+    int *fnode;       /* [2 dim][nfn] local index of the k-th node of each face (increasing) */
+    int64_t *if_el2;  /* [E][2 dim] element across each face (R11), -1 for wall faces */
+    int32_t *if_p2;   /* [E][2 dim][nfn] its local index of the coincident node */
+    double *if_A;     /* [E][2 dim][nfn][3] w_s J_s n at the face nodes */
     int64_t nwf;      /* wall faces */
     int64_t *wf_el;   /* [nwf] element */
     int *wf_fc;       /* [nwf] face 0..2dim-1 */
@@ -456,6 +472,107 @@ static int or_on_face(const oracle_sim *s, int p, int fc)
     return ijk[fc / 2] == ((fc % 2) ? s->N : 0);
 }
 
+/* Sorting of the faces by their node ids (reading R11): the ids of each face
+ * are sorted, and faces compare lexicographically on them. */
+static const int64_t *or_fkeys;
+static int or_fkey_n;
+static int or_cmp_face(const void *a, const void *b)
+{
+    const int64_t *x = or_fkeys + *(const int64_t *)a * or_fkey_n;
+    const int64_t *y = or_fkeys + *(const int64_t *)b * or_fkey_n;
+    for (int k = 0; k < or_fkey_n; ++k)
+        if (x[k] != y[k]) return x[k] < y[k] ? -1 : 1;
+    return 0;
+}
+static int or_cmp_i64(const void *a, const void *b)
+{
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+/* Interface faces of the discontinuous coupling (reading R11): every face
+ * that is not a wall is matched with the one other face carrying the same
+ * node ids, and each of its nodes with the node of the same id there. The
+ * area-weighted outward normals come from the face parametrisation (R5).
+ * Returns nonzero for an unmatched face, a face matched more than once or a
+ * face with a repeated node id. */
+static int or_dg_faces(oracle_sim *s, const double *xyz)
+{
+    int nface = s->nface, np = s->np, n1 = s->n1;
+    int nfn = (s->dim == 2) ? n1 : n1 * n1;
+    int64_t nf = s->E * nface;
+    s->nfn = nfn;
+    s->fnode = (int *)malloc(sizeof(int) * nface * nfn);
+    s->if_el2 = (int64_t *)malloc(sizeof(int64_t) * nf);
+    s->if_p2 = (int32_t *)malloc(sizeof(int32_t) * nf * nfn);
+    s->if_A = (double *)calloc((size_t)nf * nfn * 3, sizeof(double));
+    int64_t *keys = (int64_t *)malloc(sizeof(int64_t) * nf * nfn);
+    int64_t *order = (int64_t *)malloc(sizeof(int64_t) * nf);
+    int rc = 1;
+    if (!s->fnode || !s->if_el2 || !s->if_p2 || !s->if_A || !keys || !order) goto done;
+    for (int fc = 0; fc < nface; ++fc) {
+        int k = 0;
+        for (int p = 0; p < np; ++p)
+            if (or_on_face(s, p, fc)) s->fnode[fc * nfn + k++] = p;
+    }
+    int64_t nin = 0;
+    for (int64_t f = 0; f < nf; ++f) {
+        int64_t el = f / nface;
+        int fc = (int)(f % nface);
+        s->if_el2[f] = -1;
+        if (s->ftag[f] > 0) continue;
+        int64_t *kf = keys + nin * nfn;
+        for (int k = 0; k < nfn; ++k) kf[k] = s->gid[el * np + s->fnode[fc * nfn + k]];
+        qsort(kf, (size_t)nfn, sizeof(int64_t), or_cmp_i64);
+        for (int k = 1; k < nfn; ++k)
+            if (kf[k] == kf[k - 1]) goto done; /* repeated id on one face */
+        order[nin++] = f;
+    }
+    /* sort the face numbers by key; keys are stored in face-list order */
+    {
+        int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (nin > 0 ? nin : 1));
+        if (!idx) goto done;
+        for (int64_t i = 0; i < nin; ++i) idx[i] = i;
+        or_fkeys = keys;
+        or_fkey_n = nfn;
+        qsort(idx, (size_t)nin, sizeof(int64_t), or_cmp_face);
+        for (int64_t i = 0; i < nin;) {
+            int64_t j = i + 1;
+            while (j < nin && or_cmp_face(&idx[i], &idx[j]) == 0) ++j;
+            if (j - i != 2) {
+                free(idx);
+                goto done; /* unmatched, or more than two faces with these ids */
+            }
+            int64_t fa = order[idx[i]], fb = order[idx[i + 1]];
+            s->if_el2[fa] = fb / nface;
+            s->if_el2[fb] = fa / nface;
+            for (int side = 0; side < 2; ++side) {
+                int64_t f1 = side ? fb : fa, f2 = side ? fa : fb;
+                int64_t el1 = f1 / nface, el2 = f2 / nface;
+                int fc1 = (int)(f1 % nface), fc2 = (int)(f2 % nface);
+                for (int k = 0; k < nfn; ++k) {
+                    int p = s->fnode[fc1 * nfn + k];
+                    int64_t gk = s->gid[el1 * np + p];
+                    int found = -1;
+                    for (int k2 = 0; k2 < nfn; ++k2) {
+                        int p2 = s->fnode[fc2 * nfn + k2];
+                        if (s->gid[el2 * np + p2] == gk) found = p2;
+                    }
+                    s->if_p2[f1 * nfn + k] = found;
+                    or_face_normal(s, xyz, el1, fc1, p, s->if_A + (f1 * nfn + k) * 3);
+                }
+            }
+            i = j;
+        }
+        free(idx);
+    }
+    rc = 0;
+done:
+    free(keys);
+    free(order);
+    return rc;
+}
+
 void oracle_destroy(oracle_sim *s)
 {
     if (!s) return;
@@ -466,6 +583,10 @@ void oracle_destroy(oracle_sim *s)
     free(s->wJ);
     free(s->G);
     free(s->Mg);
+    free(s->fnode);
+    free(s->if_el2);
+    free(s->if_p2);
+    free(s->if_A);
     free(s->wf_el);
     free(s->wf_fc);
     free(s->wf_tag);
@@ -505,16 +626,18 @@ int oracle_get_threads(void)
 
 /* Create the oracle for a mesh and the physical parameters.
  *   filter_type 0 none, 1 quadratic, 2 exponential (reading R8);
- *   rk 0 SSPRK3, 1 printed four-stage form (reading R7).
+ *   rk 0 SSPRK3, 1 printed four-stage form (reading R7);
+ *   coupling 0 continuous Galerkin (R4), 1 discontinuous Galerkin (R11).
  * Returns NULL on invalid input, J <= 0 or allocation failure. */
 oracle_sim *oracle_create(int dim, int N, int64_t E, const double *xyz, const int64_t *gid,
                           const int32_t *face_tag, int ntags, const double *wall_u, int Q,
                           double rho0, double nu, double dt, const double *g, int filter_type,
-                          int kc, double famp, double forder, int rk)
+                          int kc, double famp, double forder, int rk, int coupling)
 {
     if ((dim != 2 && dim != 3) || N < 1 || N + 1 > OR_MAXN1 || E < 1 || dt <= 0.0 || nu <= 0.0)
         return NULL;
     if (rk != 0 && rk != 1) return NULL;
+    if (coupling != 0 && coupling != 1) return NULL;
     oracle_sim *s = (oracle_sim *)calloc(1, sizeof(oracle_sim));
     if (!s) return NULL;
     s->dim = dim;
@@ -577,6 +700,14 @@ oracle_sim *oracle_create(int dim, int N, int64_t E, const double *xyz, const in
         for (int c = 0; c < dim; ++c) s->wall_u[3 * k + c] = wall_u[k * dim + c];
 
     if (or_geometry(s, xyz)) goto fail;
+
+    /* Discontinuous coupling (reading R11): the elements across the faces,
+     * then one assembly id per local node (no sharing). */
+    s->dg = coupling;
+    if (s->dg) {
+        if (or_dg_faces(s, xyz)) goto fail;
+        for (int64_t i = 0; i < nl; ++i) s->gid[i] = i;
+    }
 
     /* Assembled lumped mass by global node (reading R4). */
     for (int64_t i = 0; i < nl; ++i) s->Mg[s->gid[i]] += s->wJ[i];
@@ -723,6 +854,28 @@ static void or_rhs_local(const oracle_sim *s, const double *f, double *rt)
             }
         }
     }
+    if (!s->dg) return;
+    /* discontinuous coupling (reading R11): upwind flux of the entering
+     * velocities on every interface face */
+#pragma omp parallel for schedule(static)
+    for (int64_t el = 0; el < s->E; ++el)
+        for (int fc = 0; fc < s->nface; ++fc) {
+            int64_t fi = el * s->nface + fc, el2 = s->if_el2[fi];
+            if (el2 < 0) continue;
+            for (int k = 0; k < s->nfn; ++k) {
+                int p = s->fnode[fc * s->nfn + k], p2 = s->if_p2[fi * s->nfn + k];
+                const double *A = s->if_A + (fi * s->nfn + k) * 3;
+                for (int a = 0; a < Q; ++a) {
+                    const double *e = s->e + 3 * a;
+                    double ne = A[0] * e[0] + A[1] * e[1] + A[2] * e[2];
+                    if (ne < 0.0) {
+                        double fin = f[el * (int64_t)Q * np + (int64_t)a * np + p];
+                        double fout = f[el2 * (int64_t)Q * np + (int64_t)a * np + p2];
+                        rt[el * (int64_t)Q * np + (int64_t)a * np + p] += ne * (fin - fout);
+                    }
+                }
+            }
+        }
 }
 
 /* Direct stiffness summation (reading R4): r = (sum over copies of rt) /

@@ -200,6 +200,7 @@ class Case:
     filter_amp: float = 0.0
     filter_order: float = 2.0
     rk: str = "ssprk3"
+    coupling: str = "cg"  # "cg" (continuous, the paper's) or "dg" (discontinuous, upwind interface flux)
     meta: dict = field(default_factory=dict)
 
     # convenience views
