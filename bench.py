@@ -16,6 +16,7 @@ times the FP64 CPU oracle on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -205,6 +206,10 @@ def main():
         k, w = max(20, args.steps // 2), max(5, args.warmup // 2)
         print(f"[bench] timing fp32dev+closure: {w} warmup + {k} steps", file=sys.stderr, flush=True)
         forms["fp32dev+closure"] = time_form(case, "fp32dev", k, w, torch, closure=blob)
+        # discontinuous coupling on the same workload: every element keeps its
+        # own face nodes and the elements couple through upwind face fluxes
+        print(f"[bench] timing fp32dev+dg: {w} warmup + {k} steps", file=sys.stderr, flush=True)
+        forms["fp32dev+dg"] = time_form(dataclasses.replace(case, coupling="dg"), "fp32dev", k, w, torch)
 
     head = forms[args.precision]
     info = head["info"]

@@ -101,6 +101,20 @@ typedef struct sel_params {
  * Returns SEL_EINVAL, SEL_EUNSUPPORTED or SEL_ENOMEM on failure. */
 int sel_mesh_create(int32_t dim, int32_t N, int64_t E, const double *xyz, const int64_t *gid,
                     const int32_t *face_tag, int32_t ntags, const double *wall_u, sel_mesh **out);
+
+/* Discontinuous-Galerkin coupling of the elements (the alternative to the
+ * continuous method that the paper's introduction discusses): same
+ * arguments and checks as sel_mesh_create, but no node is shared. Every
+ * element keeps its own copy of its face nodes with its own lumped mass wJ,
+ * gid only identifies the coincident node across each face, and every face
+ * that is not a wall adds the upwind flux of the velocities entering the
+ * element, (n.e_a) w_s J_s (f_a - f_a^across) for n.e_a < 0 (wall faces keep
+ * the FBB term of Sec. 2.2.1). Initial rho and u may differ between copies.
+ * Extra errors (SEL_EINVAL): a face that is not a wall must share its set of
+ * node ids with exactly one other face, and no face may repeat a node id
+ * (one element along a periodic direction). */
+int sel_mesh_create_dg(int32_t dim, int32_t N, int64_t E, const double *xyz, const int64_t *gid,
+                       const int32_t *face_tag, int32_t ntags, const double *wall_u, sel_mesh **out);
 int sel_mesh_destroy(sel_mesh *mesh);
 
 /* info[0..7] = dim, N, E, np, unique nodes, shared-node groups on element

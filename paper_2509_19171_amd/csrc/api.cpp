@@ -41,7 +41,7 @@ constexpr size_t kAlign = 256;
 struct Plan {
     size_t total = 0;
     size_t tabD, tabF, tabW, geoD, geoW, pcode, bpos, xyz, wJ, J, Gm, invw, invMb, bmap, bown, goff, gmem, ftag,
-        wallu, f[4], rtb, rhoc, io, red, flag, posmap, hidx, cl_params = 0, cl_X = 0, cl_dtau = 0;
+        wallu, f[4], rtb, rhoc, io, red, flag, posmap, hidx, nbr = 0, cl_params = 0, cl_X = 0, cl_dtau = 0;
     int nred = 0;
     bool closure = false;
 };
@@ -125,6 +125,7 @@ Plan make_plan(const sel_mesh *m, const sel_params *p)
     for (int i = 0; i < 4; ++i) L.f[i] = carve(c, ts * (size_t)nstate);
     L.rtb = carve(c, ts * (size_t)p->Q * (size_t)m->plane);
     L.posmap = carve(c, 4 * (size_t)(E * m->nbe));
+    if (m->dg) L.nbr = carve(c, 4 * m->nbr.size());
     L.hidx = carve(c, 4 * (size_t)(m->ngrp + 1));
     L.rhoc = carve(c, ts * (size_t)Gtot);
     L.io = carve(c, 8 * (size_t)(E * np * (m->dim + 1)));
@@ -302,6 +303,10 @@ extern "C" int sel_init(const sel_mesh *m, const sel_params *p, const double *rh
     for (int i = 0; i < 4; ++i) s->f[i] = b + L.f[i];
     s->rtb = b + L.rtb;
     s->posmap = reinterpret_cast<int32_t *>(b + L.posmap);
+    if (m->dg) {
+        s->nbr = reinterpret_cast<int32_t *>(b + L.nbr);
+        s->nfn = m->nfn;
+    }
     s->hidx = reinterpret_cast<int32_t *>(b + L.hidx);
     s->plane = m->plane;
     s->ngp = m->ngp;
@@ -342,6 +347,7 @@ extern "C" int sel_init(const sel_mesh *m, const sel_params *p, const double *rh
     UP(s->gmem, m->gmem.data(), 4 * m->gmem.size());
     UP(s->ftag, m->ftag.data(), 4 * m->ftag.size());
     UP(s->posmap, m->posmap.data(), 4 * m->posmap.size());
+    if (m->dg) UP(s->nbr, m->nbr.data(), 4 * m->nbr.size());
     UP(s->hidx, m->hidx.data(), 4 * m->hidx.size());
     UP(s->io, rho, 8 * nl);
     UP(s->io + nl, u, 8 * nl * m->dim);

@@ -298,6 +298,32 @@ __device__ __forceinline__ void wall_flux(T &rt, T v, T vb, const T (&Gr)[DIM][D
     }
 }
 
+// Upwind interface flux of velocity a under the discontinuous coupling,
+// added to rt: on each face through the node that is not a wall (icode:
+// bit 2m set for direction m, bit 2m+1 for the face r_m = +1) and where e_a
+// enters the element, (n.e_a) w_s J_s (v - f_out), with f_out the value of
+// the coincident node of the element across the face (its group gnb[m] in
+// the state op) and the area vector as in wall_flux.
+template <int DIM, int N, int Q, int a, typename T>
+__device__ __forceinline__ void interface_flux(T &rt, T v, const T (&Gr)[DIM][DIM], uint32_t icode,
+                                               const int32_t (&gnb)[DIM], const T *op, int64_t QGi)
+{
+    constexpr int ex = lat_e<DIM, Q>(a, 0), ey = lat_e<DIM, Q>(a, 1), ez = lat_e<DIM, Q>(a, 2);
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) {
+        if ((icode >> (2 * m)) & 1u) {
+            const T sc = (((icode >> (2 * m + 1)) & 1u) ? T(1) : T(-1)) * T(N * (N + 1)) / T(2);
+            T ne = T(ex) * Gr[m][0] + T(ey) * Gr[m][1];
+            if constexpr (DIM == 3) ne += T(ez) * Gr[m][2];
+            ne *= sc;
+            if (ne < T(0)) {
+                const SIdx so = sidx_group(gnb[m], Q, QGi);
+                rt += ne * (v - op[so.base + (int64_t)a * so.stride]);
+            }
+        }
+    }
+}
+
 // ----------------------------------------------------------- stage kernel --
 enum { M_STAGE1 = 0, M_STAGE23 = 1, M_LOCAL = 2, M_FILTER = 3 };
 
@@ -324,9 +350,13 @@ struct StageArgs {
     int filter;    // M_STAGE1: filter the operand first
     T tau;                // relaxation time
     const float *dtau;    // learned-closure increments per node id (nullptr: plain method)
+    const int32_t *nbr;   // discontinuous coupling: [E][2 dim][(N+1)^(dim-1)] group across each face (nullptr: continuous)
+    int collide_only;     // M_STAGE1: stop after writing the post-collision state
 };
 
-template <int DIM, int N, int Q, typename T, bool DEV, int MODE>
+// DGC: the discontinuous coupling's interface flux is compiled in (a
+// separate instantiation, so the continuous kernels carry none of it).
+template <int DIM, int N, int Q, typename T, bool DEV, int MODE, bool DGC = false>
 __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK), (((MODE == M_STAGE23 || MODE == M_STAGE1) && sizeof(T) == 4) ? 4 : 1)) k_stage(StageArgs<T> A)
 {
     using GG = Geo<DIM, N>;
@@ -562,6 +592,7 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK), (((MODE == M_STAGE23 || 
                 A.rhoc[gix] = rho;
             }
         }
+        if (A.collide_only) return;  // whole workgroup
     } else if constexpr (MODE == M_STAGE23) {
         if (valid && inner) rho = A.rhoc[gix];
     }
@@ -598,6 +629,28 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK), (((MODE == M_STAGE23 || 
         }
     }
 
+    // interface faces through this node under the discontinuous coupling
+    // (faces that are not walls) and the group of the coincident node across
+    // each; face nodes are numbered in increasing node index
+    uint32_t icode = 0;
+    int32_t gnb[DIM] = {};
+    if (DGC && valid && !inner) {
+        constexpr int nfn = (DIM == 2) ? n1 : n1 * n1;
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) {
+            const int idx = (m == 0) ? i : (m == 1) ? j : k;
+            if (idx == 0 || idx == N) {
+                const int fc = 2 * m + (idx == N ? 1 : 0);
+                if (A.ftag[e * 2 * DIM + fc] == 0) {
+                    const int t0 = (m == 0) ? j : i;
+                    const int t1 = (DIM == 2) ? 0 : (m == 2) ? j : k;
+                    gnb[m] = A.nbr[(e * 2 * DIM + fc) * nfn + t0 + n1 * t1];
+                    icode |= (1u | (idx == N ? 2u : 0u)) << (2 * m);
+                }
+            }
+        }
+    }
+
     // streaming operator per velocity (Sec. 2.2): P is the velocity's plane in
     // LDS, v and f0v the node's operand and post-collision values
     auto velocity = [&](auto AA, const T *P, T v, T f0v) {
@@ -610,6 +663,9 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK), (((MODE == M_STAGE23 || 
             else if constexpr (ALLQ || FULL) vb = fq[b];
             else vb = A.op[si.base + (int64_t)b * si.stride];
             wall_flux<DIM, N, Q, a>(rt, v, vb, Gr, wcode, A.wallu, A.rho0);
+        }
+        if constexpr (DGC) {
+            if (icode) interface_flux<DIM, N, Q, a>(rt, v, Gr, icode, gnb, A.op, A.QGi);
         }
         if constexpr (STG) {
             // kept in the register of the consumed operand, stored after the loop

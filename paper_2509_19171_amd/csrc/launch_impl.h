@@ -51,6 +51,7 @@ struct Impl {
         A.ftag = s->ftag;
         A.bown = s->bown;
         A.wallu = static_cast<const T *>(s->wallu);
+        A.nbr = s->nbr;
         A.E = s->E;
         A.nblk = nblk(s);
         A.Gi = s->Gi;
@@ -110,7 +111,12 @@ struct Impl {
         hipEvent_t ev = nullptr;
         const int kind = (MODE == M_STAGE1) ? 0 : (MODE == M_STAGE23) ? 1 : 3;
         if (int rc = tic(s, kind, ev)) return rc;
-        hipLaunchKernelGGL((k_stage<DIM, N, Q, T, DEV, MODE>), grid, block, 0, s->stream, A);
+        bool dg = false;  // streaming with the discontinuous coupling's interface flux
+        if constexpr (MODE == M_STAGE23 || MODE == M_LOCAL) dg = A.nbr != nullptr;
+        if constexpr (MODE == M_STAGE23 || MODE == M_LOCAL) {
+            if (dg) hipLaunchKernelGGL((k_stage<DIM, N, Q, T, DEV, MODE, true>), grid, block, 0, s->stream, A);
+        }
+        if (!dg) hipLaunchKernelGGL((k_stage<DIM, N, Q, T, DEV, MODE>), grid, block, 0, s->stream, A);
         SEL_LAUNCH_CHECK();
         return toc(s, ev);
     }
@@ -182,6 +188,38 @@ struct Impl {
         return launch_group(s, B);
     }
 
+    // First stage: filter (when pending) and collide the state S into the
+    // post-collision state y = F0, then FA = y + cc L(y). The continuous
+    // coupling streams in the same kernel (a shared node's post-collision
+    // value is the same in every element); the discontinuous coupling needs
+    // the post-collision values across faces and streams in a second pass.
+    static int stage_one(sel_sim *s, StageArgs<T> &A, GroupArgs<T> &B, const T *S, T *F0, T *FA, double cc,
+                         bool pending)
+    {
+        A.op = S;
+        A.f0out = F0;
+        A.out = FA;
+        A.ca = T(0);
+        A.cb = T(1);
+        A.cc = T(cc);
+        A.filter = pending ? 1 : 0;
+        if (s->nbr) {
+            A.collide_only = 1;
+            const int rc = launch_stage<M_STAGE1>(s, A);
+            A.collide_only = 0;
+            if (rc) return rc;
+            return stage_pass(s, A, B, F0, F0, FA, 0.0, 1.0, cc);
+        }
+        if (int rc = launch_stage<M_STAGE1>(s, A)) return rc;
+        B.f0 = F0;
+        B.fk = F0;
+        B.out = FA;
+        B.ca = T(0);
+        B.cb = T(1);
+        B.cc = T(cc);
+        return launch_group(s, B);
+    }
+
     // The four printed stage formulas of Sec. 2.2.2 with L applied linearly
     // to their combinations (stage values w1..w3, y the post-collision state):
     //   w1 = y + dt/3 L(y)
@@ -199,21 +237,7 @@ struct Impl {
     static int printed4(sel_sim *s, StageArgs<T> &A, GroupArgs<T> &B, T *S, T *FB, T *F0, T *FA, bool pending)
     {
         const double dt = s->p.dt;
-        A.op = S;
-        A.f0out = F0;
-        A.out = FA;
-        A.ca = T(0);
-        A.cb = T(1);
-        A.cc = T(dt / 3.0);
-        A.filter = pending ? 1 : 0;
-        if (int rc = launch_stage<M_STAGE1>(s, A)) return rc;
-        B.f0 = F0;
-        B.fk = F0;
-        B.out = FA;
-        B.ca = T(0);
-        B.cb = T(1);
-        B.cc = T(dt / 3.0);
-        if (int rc = launch_group(s, B)) return rc;
+        if (int rc = stage_one(s, A, B, S, F0, FA, dt / 3.0, pending)) return rc;
         if (int rc = stage_pass(s, A, B, FA, F0, FB, 9.0 / 4.0, -5.0 / 4.0, 0.75 * dt)) return rc;
         if (int rc = stage_pass(s, A, B, FB, FA, F0, 8.0 / 9.0, 1.0 / 9.0, 2.0 / 3.0 * dt)) return rc;
         return stage_pass(s, A, B, F0, FB, S, 3.0 / 8.0, 5.0 / 8.0, 0.25 * dt);
@@ -256,21 +280,7 @@ struct Impl {
                 continue;
             }
             // stage 1: f1 = f0 + dt L(f0), f0 = collide(filter(f3_prev) or f-bar)
-            A.op = S;
-            A.f0out = F0;
-            A.out = FA;
-            A.ca = T(0);
-            A.cb = T(1);
-            A.cc = T(dt);
-            A.filter = pending ? 1 : 0;
-            if (int rc = launch_stage<M_STAGE1>(s, A)) return rc;
-            B.f0 = F0;
-            B.fk = F0;
-            B.out = FA;
-            B.ca = T(0);
-            B.cb = T(1);
-            B.cc = T(dt);
-            if (int rc = launch_group(s, B)) return rc;
+            if (int rc = stage_one(s, A, B, S, F0, FA, dt, pending)) return rc;
             // stage 2: f2 = 3/4 f0 + 1/4 (f1 + dt L(f1))
             A.op = FA;
             A.f0in = F0;

@@ -17,8 +17,10 @@ static int ipow(int b, int e)
     return r;
 }
 
-extern "C" int sel_mesh_create(int32_t dim, int32_t N, int64_t E, const double *xyz, const int64_t *gid,
-                               const int32_t *face_tag, int32_t ntags, const double *wall_u, sel_mesh **out)
+static int build_interfaces(sel_mesh *m);
+
+static int mesh_create(int32_t dim, int32_t N, int64_t E, const double *xyz, const int64_t *gid,
+                       const int32_t *face_tag, int32_t ntags, const double *wall_u, int dg, sel_mesh **out)
 {
     if (!out || !xyz || !gid) {
         set_error("sel_mesh_create: null pointer argument");
@@ -136,7 +138,8 @@ extern "C" int sel_mesh_create(int32_t dim, int32_t N, int64_t E, const double *
         for (int64_t e = 0; e < E; ++e)
             for (int b = 0; b < m->nbe; ++b) {
                 int64_t lb = e * m->nbe + b;
-                key[lb] = {gid[e * m->np + m->bpos[b]], (int32_t)lb};
+                // the discontinuous coupling shares no node: one group each
+                key[lb] = {dg ? lb : gid[e * m->np + m->bpos[b]], (int32_t)lb};
             }
         std::sort(key.begin(), key.end());
         std::vector<int64_t> run_start;
@@ -205,6 +208,13 @@ extern "C" int sel_mesh_create(int32_t dim, int32_t N, int64_t E, const double *
                 used[q] = 1;
             }
         }
+        m->dg = dg;
+        if (dg) {
+            if (int rc = build_interfaces(m)) {
+                delete m;
+                return rc;
+            }
+        }
     } catch (const std::bad_alloc &) {
         set_error("sel_mesh_create: out of host memory");
         delete m;
@@ -212,6 +222,85 @@ extern "C" int sel_mesh_create(int32_t dim, int32_t N, int64_t E, const double *
     }
     *out = m;
     return SEL_OK;
+}
+
+// Interfaces of the discontinuous coupling: every face that is not a wall is
+// paired with the one other face carrying the same set of node ids, and each
+// of its nodes with the node of equal id there.
+static int build_interfaces(sel_mesh *m)
+{
+    const int n1 = m->n1, np = m->np, nface = m->nface, N = m->N;
+    const int nfn = m->dim == 2 ? n1 : n1 * n1;
+    const int64_t nf = m->E * nface;
+    m->nfn = nfn;
+    std::vector<std::vector<int>> fnode(nface);
+    for (int p = 0; p < np; ++p) {
+        const int ijk[3] = {p % n1, (p / n1) % n1, p / (n1 * n1)};
+        for (int d = 0; d < m->dim; ++d) {
+            if (ijk[d] == 0) fnode[2 * d].push_back(p);
+            if (ijk[d] == N) fnode[2 * d + 1].push_back(p);
+        }
+    }
+    std::vector<int64_t> ids((size_t)nf * nfn);
+    std::vector<int64_t> faces;
+    for (int64_t f = 0; f < nf; ++f) {
+        if (m->ftag[f] > 0) continue;
+        const int64_t e = f / nface;
+        const int fc = (int)(f % nface);
+        int64_t *v = ids.data() + f * nfn;
+        for (int k = 0; k < nfn; ++k) v[k] = m->gid[e * np + fnode[fc][k]];
+        std::sort(v, v + nfn);
+        if (std::adjacent_find(v, v + nfn) != v + nfn) {
+            set_error("sel_mesh_create_dg: a face repeats a node id (one element along a periodic direction)");
+            return SEL_EINVAL;
+        }
+        faces.push_back(f);
+    }
+    auto less = [&](int64_t a, int64_t b) {
+        return std::lexicographical_compare(ids.begin() + a * nfn, ids.begin() + (a + 1) * nfn, ids.begin() + b * nfn,
+                                            ids.begin() + (b + 1) * nfn);
+    };
+    auto same = [&](int64_t a, int64_t b) { return std::equal(ids.begin() + a * nfn, ids.begin() + (a + 1) * nfn,
+                                                              ids.begin() + b * nfn); };
+    std::sort(faces.begin(), faces.end(), less);
+    m->nbr.assign((size_t)nf * nfn, -1);
+    for (size_t i = 0; i < faces.size(); i += 2) {
+        if (i + 1 >= faces.size() || !same(faces[i], faces[i + 1]) ||
+            (i + 2 < faces.size() && same(faces[i], faces[i + 2]))) {
+            set_error("sel_mesh_create_dg: a face that is not a wall has no single partner face");
+            return SEL_EINVAL;
+        }
+        for (int side = 0; side < 2; ++side) {
+            const int64_t fa = faces[i + side], fb = faces[i + 1 - side];
+            const int64_t ea = fa / nface, eb = fb / nface;
+            const int fca = (int)(fa % nface), fcb = (int)(fb % nface);
+            for (int k = 0; k < nfn; ++k) {
+                const int64_t g = m->gid[ea * np + fnode[fca][k]];
+                int pb = -1;
+                for (int q : fnode[fcb])
+                    if (m->gid[eb * np + q] == g) pb = q;
+                if (pb < 0) {
+                    set_error("sel_mesh_create_dg: internal error in the face matching");
+                    return SEL_EINVAL;
+                }
+                const int bsl = -m->pcode[pb] - 1;
+                m->nbr[fa * nfn + k] = m->bmap[eb * m->nbe + bsl];
+            }
+        }
+    }
+    return SEL_OK;
+}
+
+extern "C" int sel_mesh_create(int32_t dim, int32_t N, int64_t E, const double *xyz, const int64_t *gid,
+                               const int32_t *face_tag, int32_t ntags, const double *wall_u, sel_mesh **out)
+{
+    return mesh_create(dim, N, E, xyz, gid, face_tag, ntags, wall_u, 0, out);
+}
+
+extern "C" int sel_mesh_create_dg(int32_t dim, int32_t N, int64_t E, const double *xyz, const int64_t *gid,
+                                  const int32_t *face_tag, int32_t ntags, const double *wall_u, sel_mesh **out)
+{
+    return mesh_create(dim, N, E, xyz, gid, face_tag, ntags, wall_u, 1, out);
 }
 
 extern "C" int sel_mesh_destroy(sel_mesh *mesh)

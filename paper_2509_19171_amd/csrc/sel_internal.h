@@ -65,6 +65,12 @@ struct sel_mesh {
     int maxm = 0;
     std::vector<int32_t> posmap;  // [E][nbe] slot of each element-boundary node
     std::vector<int32_t> hidx;    // [ngrp] index among groups with > 2 members, or -1
+    // discontinuous coupling: no node is shared (one group per element-
+    // boundary node); nbr holds, for every face node of every face that is
+    // not a wall, the group of the coincident node in the element across it
+    int dg = 0;
+    int nfn = 0;                  // nodes per face, (N+1)^(dim-1)
+    std::vector<int32_t> nbr;     // [E][2 dim][nfn], face nodes in increasing node index; -1 on walls
 };
 
 // Device arrays of a simulation, all carved out of one workspace.
@@ -102,6 +108,8 @@ struct sel_sim {
     int32_t *ftag = nullptr;   // [E][2 dim]
     int32_t *posmap = nullptr; // [E][nbe] contribution slot
     int32_t *hidx = nullptr;   // [ngrp]
+    int32_t *nbr = nullptr;    // discontinuous coupling: [E][2 dim][nfn] group across each face, or nullptr
+    int nfn = 0;
     int64_t plane = 0, ngp = 0, nmp = 0;
     void *wallu = nullptr;     // T [ntags+1][3], row 0 = zero
     void *f[4] = {};           // T [nstate]: state, f0, stage a, stage b

@@ -62,6 +62,7 @@ def load():
     P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     sigs = {
         "sel_mesh_create": [I32, I32, I64, P, P, P, I32, P, P],
+        "sel_mesh_create_dg": [I32, I32, I64, P, P, P, I32, P, P],
         "sel_mesh_destroy": [P],
         "sel_mesh_info": [P, P],
         "sel_workspace_bytes": [P, P, P],
@@ -122,7 +123,8 @@ def version() -> str:
 class Mesh:
     """sel_mesh_create / sel_mesh_destroy."""
 
-    def __init__(self, dim, N, xyz, gid, face_tag=None, wall_u=None):
+    def __init__(self, dim, N, xyz, gid, face_tag=None, wall_u=None, coupling="cg"):
+        """coupling "cg" (sel_mesh_create) or "dg" (sel_mesh_create_dg)."""
         lib = load()
         self.dim, self.N = int(dim), int(N)
         self.np_ = (self.N + 1) ** self.dim
@@ -134,15 +136,15 @@ class Mesh:
         wu = wu.reshape(-1, self.dim)
         ntags = int(wu.shape[0])
         h = ctypes.c_void_p()
-        _check(lib.sel_mesh_create(self.dim, self.N, self.E, _ptr(xyz), _ptr(gid),
-                                   _ptr(ft) if ft is not None else None, ntags,
-                                   _ptr(wu) if ntags else None, ctypes.byref(h)))
+        create = {"cg": lib.sel_mesh_create, "dg": lib.sel_mesh_create_dg}[coupling]
+        _check(create(self.dim, self.N, self.E, _ptr(xyz), _ptr(gid), _ptr(ft) if ft is not None else None,
+                      ntags, _ptr(wu) if ntags else None, ctypes.byref(h)))
         self._h = h
         self._lib = lib
 
     @classmethod
-    def from_inputs(cls, mesh):
-        return cls(mesh.dim, mesh.N, mesh.xyz, mesh.gid, mesh.face_tag, mesh.wall_u)
+    def from_inputs(cls, mesh, coupling="cg"):
+        return cls(mesh.dim, mesh.N, mesh.xyz, mesh.gid, mesh.face_tag, mesh.wall_u, coupling)
 
     def info(self) -> dict:
         out = np.zeros(8, dtype=np.int64)
@@ -338,7 +340,7 @@ def params_from_case(case, precision="fp64") -> sel_params:
 
 def from_case(case, precision="fp64", device="cuda:0", rho=None, u=None, stream=None, closure=None) -> Sim:
     """GPU simulation of a case from the seeded input generators."""
-    mesh = Mesh.from_inputs(case.mesh)
+    mesh = Mesh.from_inputs(case.mesh, case.coupling)
     p = params_from_case(case, precision)
     if closure is not None:
         blob = np.ascontiguousarray(closure, dtype=np.float32).reshape(-1)

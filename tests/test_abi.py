@@ -98,3 +98,28 @@ def test_binding_refuses_missing_library(monkeypatch, tmp_path):
     monkeypatch.setattr(sel, "LIB_PATH", str(tmp_path / "libsel.so"))
     with pytest.raises(RuntimeError):
         sel.load()
+
+
+def test_mesh_create_dg_ingest():
+    """The discontinuous coupling shares no node, and faces must pair up."""
+    m = I.box_mesh(2, 4, (3, 2), (0, 0), (1, 1), (True, True))
+    cg = sel.Mesh.from_inputs(m).info()
+    dg = sel.Mesh.from_inputs(m, "dg").info()
+    assert cg["unique_nodes"] < m.E * m.np_
+    assert dg["unique_nodes"] == m.E * m.np_
+    assert dg["groups"] == m.E * dg["boundary_nodes_per_element"]
+    # walls are not interfaces: a channel with two wall sides is accepted
+    ch = I.box_mesh(3, 3, (2, 2, 2), (0, 0, 0), (1, 1, 1), (True, False, True), wall_tags={1: (1, 1)},
+                    wall_u=[[0, 0, 0]])
+    assert sel.Mesh.from_inputs(ch, "dg").info()["wall_faces"] == 8
+    # one element along a periodic direction: a face repeats a node id
+    one = I.box_mesh(2, 4, (1, 3), (0, 0), (1, 1), (True, True))
+    with pytest.raises(sel.SelError) as ex:
+        sel.Mesh.from_inputs(one, "dg")
+    assert ex.value.code == sel.SEL_EINVAL
+    sel.Mesh.from_inputs(one)  # the continuous coupling accepts it
+    # open boundary faces have no partner
+    opn = I.box_mesh(2, 4, (2, 2), (0, 0), (1, 1), (False, False), wall_tags={0: (0, 0), 1: (0, 0)})
+    with pytest.raises(sel.SelError) as ex:
+        sel.Mesh.from_inputs(opn, "dg")
+    assert ex.value.code == sel.SEL_EINVAL
