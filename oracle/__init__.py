@@ -58,6 +58,7 @@ def _load():
     lib.oracle_set_f.argtypes = [P, P]
     lib.oracle_geometry.argtypes = [P, P, P, P]
     lib.oracle_mass.argtypes = [P, P]
+    lib.oracle_set_force.argtypes = [P, P]
     for name in ("oracle_rhs_local", "oracle_rhs", "oracle_collide", "oracle_filter"):
         getattr(lib, name).argtypes = [P, P, P]
     lib.oracle_time.restype = D
@@ -239,6 +240,16 @@ class OracleSim:
         J = np.zeros((self.E, self.np_))
         self._lib.oracle_geometry(self._h, _ptr(wJ), _ptr(G), _ptr(J))
         return wJ, G, J
+
+    def set_force(self, F):
+        """Force density per node [E][np][dim] added to rho g from the next
+        step on; None removes it."""
+        if F is None:
+            self._lib.oracle_set_force(self._h, None)
+            return
+        self._F = _f64(F).reshape(self.E, self.np_, self.dim)
+        if self._lib.oracle_set_force(self._h, _ptr(self._F)):
+            raise MemoryError("oracle_set_force")
 
     def mass(self):
         M = np.zeros((self.E, self.np_))

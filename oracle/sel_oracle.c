@@ -53,6 +53,10 @@
  *       id); wall faces keep the FBB term of R5. A face whose nodes repeat an
  *       id (one element along a periodic direction) is rejected: its
  *       coincident nodes would be ambiguous.
+ *   R12 The force density of Sec. 2.1 is F = rho g + F_n(x): a body
+ *       acceleration plus an optional force density per node (the pipe case
+ *       of Sec. 3.5 adds a perturbation force of this kind). Like rho g it
+ *       is taken at the collision of the step and frozen for its stages.
  *
  * Conventions shared with the public interface (the interface documents
  * them; this file re-states them in its own code):
@@ -330,6 +334,7 @@ typedef struct oracle_sim {
     double *rg;       /* [Q][E np] assembled sums by global id */
     double *rhoc;     /* [E][np] density at the collision of the step */
     double *dtau;     /* [E][np] relaxation-time increments (learned closure), NULL = 0 */
+    double *Fn;       /* [E][np][3] force density added to rho g (reading R12), NULL = 0 */
     double time;
     int64_t nstep;
 } oracle_sim;
@@ -603,6 +608,7 @@ void oracle_destroy(oracle_sim *s)
     free(s->rg);
     free(s->rhoc);
     free(s->dtau);
+    free(s->Fn);
     free(s);
 }
 
@@ -795,7 +801,7 @@ static void or_collide_all(const oracle_sim *s, const double *fb, double *fs, do
             const double *fn = fb + el * (int64_t)Q * np + p;
             double rho, u[3], F[3];
             or_moments_node(s, fn, np, &rho, u);
-            for (int k = 0; k < 3; ++k) F[k] = rho * s->g[k];
+            for (int k = 0; k < 3; ++k) F[k] = rho * s->g[k] + (s->Fn ? s->Fn[(el * np + p) * 3 + k] : 0.0);
             /* relaxation time, plus the closure's increment when one is set */
             double tau = s->tau + (s->dtau ? s->dtau[el * np + p] : 0.0);
             for (int a = 0; a < Q; ++a) {
@@ -909,7 +915,8 @@ static void or_L(oracle_sim *s, const double *f, double *Lf, int with_force)
     for (int64_t el = 0; el < s->E; ++el)
         for (int p = 0; p < np; ++p) {
             double F[3];
-            for (int k = 0; k < 3; ++k) F[k] = s->rhoc[el * np + p] * s->g[k];
+            for (int k = 0; k < 3; ++k)
+                F[k] = s->rhoc[el * np + p] * s->g[k] + (s->Fn ? s->Fn[(el * np + p) * 3 + k] : 0.0);
             for (int a = 0; a < Q; ++a) Lf[el * (int64_t)Q * np + (int64_t)a * np + p] += or_fs(s, a, F);
         }
 }
@@ -1159,6 +1166,25 @@ int oracle_rk_scalar(int rk, double lam, double b, double y0, double dt, int64_t
         }
     }
     *y = v;
+    return 0;
+}
+
+/* Force density per node [E][np][dim] added to rho g from the next step on
+ * (reading R12); NULL removes it. */
+int oracle_set_force(oracle_sim *s, const double *F)
+{
+    int64_t nl = s->E * s->np;
+    if (!F) {
+        free(s->Fn);
+        s->Fn = NULL;
+        return 0;
+    }
+    if (!s->Fn) {
+        s->Fn = (double *)calloc((size_t)nl * 3, sizeof(double));
+        if (!s->Fn) return -1;
+    }
+    for (int64_t i = 0; i < nl; ++i)
+        for (int k = 0; k < 3; ++k) s->Fn[i * 3 + k] = k < s->dim ? F[i * s->dim + k] : 0.0;
     return 0;
 }
 
