@@ -171,6 +171,16 @@ int sel_reduce(sel_sim *sim, double *out);
 int sel_get_f(sel_sim *sim, double *f);
 int sel_set_f(sel_sim *sim, const double *f);
 
+/* Force density per node added to the body force: F = rho g + F_n (Sec. 2.1;
+ * the pipe case of Sec. 3.5 adds a perturbation force of this kind). F is a
+ * host array [E][np][dim] (FP64); the copies of a shared node must carry
+ * equal values under the continuous coupling (the owning copy is used).
+ * Like rho g it is taken at the collision of every following step and frozen
+ * for its stages; the current state is not changed, and a time-dependent
+ * force is set again between calls of sel_step. NULL removes it. Errors:
+ * SEL_EINVAL (null sim or a non-finite entry). Synchronises. */
+int sel_set_force(sel_sim *sim, const double *F);
+
 /* Simulated time and step count. */
 int sel_get_time(const sel_sim *sim, double *t, int64_t *nstep);
 

@@ -41,7 +41,7 @@ constexpr size_t kAlign = 256;
 struct Plan {
     size_t total = 0;
     size_t tabD, tabF, tabW, geoD, geoW, pcode, bpos, xyz, wJ, J, Gm, invw, invMb, bmap, bown, goff, gmem, ftag,
-        wallu, f[4], rtb, rhoc, io, red, flag, posmap, hidx, nbr = 0, cl_params = 0, cl_X = 0, cl_dtau = 0;
+        wallu, f[4], rtb, rhoc, Fn, io, red, flag, posmap, hidx, nbr = 0, cl_params = 0, cl_X = 0, cl_dtau = 0;
     int nred = 0;
     bool closure = false;
 };
@@ -128,6 +128,7 @@ Plan make_plan(const sel_mesh *m, const sel_params *p)
     if (m->dg) L.nbr = carve(c, 4 * m->nbr.size());
     L.hidx = carve(c, 4 * (size_t)(m->ngrp + 1));
     L.rhoc = carve(c, ts * (size_t)Gtot);
+    L.Fn = carve(c, ts * 3 * (size_t)Gtot);
     L.io = carve(c, 8 * (size_t)(E * np * (m->dim + 1)));
     int64_t nred = (E * np + 255) / 256;
     if (nred > 1024) nred = 1024;
@@ -312,6 +313,7 @@ extern "C" int sel_init(const sel_mesh *m, const sel_params *p, const double *rh
     s->ngp = m->ngp;
     s->nmp = m->nmp;
     s->rhoc = b + L.rhoc;
+    s->Fn = b + L.Fn;
     s->io = reinterpret_cast<double *>(b + L.io);
     s->red = reinterpret_cast<double *>(b + L.red);
     s->nred = L.nred;
@@ -522,6 +524,27 @@ extern "C" int sel_set_f(sel_sim *s, const double *f)
                                 8 * (size_t)s->np, (size_t)s->E, hipMemcpyHostToDevice, s->stream));
         if (int rc = ops->scatter(s, a, s->io, s->f[s->cur], true)) return rc;
     }
+    return sync_check(s);
+}
+
+extern "C" int sel_set_force(sel_sim *s, const double *F)
+{
+    if (!s) {
+        set_error("sel_set_force: null sim");
+        return SEL_EINVAL;
+    }
+    if (!F) {
+        s->force_on = false;
+        return SEL_OK;
+    }
+    for (int64_t i = 0; i < s->E * (int64_t)s->np * s->dim; ++i)
+        if (!std::isfinite(F[i])) {
+            set_error("sel_set_force: non-finite force");
+            return SEL_EINVAL;
+        }
+    HIP_OK(hipMemcpyAsync(s->io, F, 8 * (size_t)s->E * s->np * s->dim, hipMemcpyHostToDevice, s->stream));
+    if (int rc = ops_of(s)->set_force(s, s->io)) return rc;
+    s->force_on = true;
     return sync_check(s);
 }
 

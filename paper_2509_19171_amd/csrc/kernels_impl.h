@@ -1173,6 +1173,98 @@ __global__ void k_gather_plane(NodeMap M, const T *src, double *dst, int a, doub
     dst[q] = double(src[si.base + (int64_t)a * si.stride]) + off;
 }
 
+// ------------------------------------------------------ per-node force --
+// A force density per node F_n is added to rho g (Sec. 2.1; F = rho g + F_n,
+// taken at the collision and frozen for the stages). Both force terms are
+// linear in F, so the per-node part is applied by two passes over the node
+// ids beside the kernels of the body force: F** after the collision, F*
+// after each stage's assembly.
+
+// state index of node id q (interior ids first, then the groups)
+__device__ __forceinline__ SIdx sidx_node(int64_t q, int64_t Gi, int NI, int Q, int64_t QGi)
+{
+    if (q < Gi) {
+        const int64_t e = q / NI;
+        return sidx_interior(e, (int)(q - e * NI), Q, NI);
+    }
+    return sidx_group(q - Gi, Q, QGi);
+}
+
+// F [E][np][dim] (FP64) -> Fn [Gtot][3] by node id, from the owning copies
+template <typename T>
+__global__ void k_force_set(NodeMap M, const double *F, int dim, T *Fn)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= M.E * M.NP) return;
+    const int64_t e = q / M.NP;
+    const int p = (int)(q - e * M.NP);
+    const int pc = M.pcode[p];
+    int64_t id;
+    if (pc >= 0) {
+        id = e * M.NI + pc;
+    } else {
+        const int b = -pc - 1;
+        if (!M.bown[e * M.NB + b]) return;
+        id = M.Gi + M.bmap[e * M.NB + b];
+    }
+    for (int k = 0; k < 3; ++k) Fn[id * 3 + k] = k < dim ? T(F[q * dim + k]) : T(0);
+}
+
+// after the collision: f*_a += (1 - omega/2) dt F**_a(u, F_n), with
+// F**_a = t_a ((e.u)(e.F)/cs4 - (u.F)/cs2) and u = j / rho of the
+// post-collision state (the collision and F** of rho g leave j unchanged)
+template <int DIM, int Q, typename T, bool DEV>
+__global__ void k_force_collide(T *f, const T *Fn, const float *dtau, int64_t Gtot, int64_t Gi, int NI,
+                                int64_t QGi, T tau, T dt, T rho0)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= Gtot) return;
+    const SIdx si = sidx_node(q, Gi, NI, Q, QGi);
+    T v[Q];
+    T m0 = 0, j0 = 0, j1 = 0, j2 = 0;
+    static_for<0, Q>([&](auto AA) {
+        constexpr int a = decltype(AA)::value;
+        v[a] = f[si.base + (int64_t)a * si.stride];
+        m0 += v[a];
+        if constexpr (lat_e<DIM, Q>(a, 0) != 0) j0 += T(lat_e<DIM, Q>(a, 0)) * v[a];
+        if constexpr (lat_e<DIM, Q>(a, 1) != 0) j1 += T(lat_e<DIM, Q>(a, 1)) * v[a];
+        if constexpr (lat_e<DIM, Q>(a, 2) != 0) j2 += T(lat_e<DIM, Q>(a, 2)) * v[a];
+    });
+    const T rho = DEV ? rho0 + m0 : m0;
+    const T u0 = j0 / rho, u1 = j1 / rho, u2 = j2 / rho;
+    const T F0 = Fn[q * 3], F1 = Fn[q * 3 + 1], F2 = Fn[q * 3 + 2];
+    const T uF = u0 * F0 + u1 * F1 + u2 * F2;
+    const T omega = T(1) / (tau + (dtau ? T(dtau[q]) : T(0)) + T(0.5));
+    const T coef = (T(1) - T(0.5) * omega) * dt;
+    static_for<0, Q>([&](auto AA) {
+        constexpr int a = decltype(AA)::value;
+        constexpr int ex = lat_e<DIM, Q>(a, 0), ey = lat_e<DIM, Q>(a, 1), ez = lat_e<DIM, Q>(a, 2);
+        const T t = T(lat_t<DIM, Q>(a));
+        const T eu = T(ex) * u0 + T(ey) * u1 + T(ez) * u2;
+        const T eF = T(ex) * F0 + T(ey) * F1 + T(ez) * F2;
+        f[si.base + (int64_t)a * si.stride] = v[a] + coef * (t * (T(9) * eu * eF - T(3) * uF));
+    });
+}
+
+// after a stage out = ca f0 + cb fk + cc L(fk): out_a += cc F*_a(F_n),
+// F*_a = t_a (e_a . F) / cs2
+template <int DIM, int Q, typename T>
+__global__ void k_force_stage(T *out, const T *Fn, int64_t Gtot, int64_t Gi, int NI, int64_t QGi, T cc)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= Gtot) return;
+    const SIdx si = sidx_node(q, Gi, NI, Q, QGi);
+    const T F0 = Fn[q * 3], F1 = Fn[q * 3 + 1], F2 = Fn[q * 3 + 2];
+    static_for<0, Q>([&](auto AA) {
+        constexpr int a = decltype(AA)::value;
+        constexpr int ex = lat_e<DIM, Q>(a, 0), ey = lat_e<DIM, Q>(a, 1), ez = lat_e<DIM, Q>(a, 2);
+        if constexpr (ex != 0 || ey != 0 || ez != 0) {
+            const T t = T(lat_t<DIM, Q>(a));
+            out[si.base + (int64_t)a * si.stride] += cc * (t * T(3) * (T(ex) * F0 + T(ey) * F1 + T(ez) * F2));
+        }
+    });
+}
+
 // moments (Eqs. pressure, momentum) in FP64 at every element node
 template <int DIM, int Q, typename T, bool DEV>
 __global__ void k_moments(NodeMap M, const T *f, double rho0, double *rho, double *u)

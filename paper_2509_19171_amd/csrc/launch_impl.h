@@ -168,6 +168,36 @@ struct Impl {
     // one time step: collide (and filter the previous step's result) ->
     // SSPRK3 streaming with F* and the wall flux; the filter of this step is
     // applied by the next step's first stage, or at the end of the call.
+    // per-node force density (added to rho g): fill from FP64 [E][np][dim]
+    static int set_force(sel_sim *s, const double *d_F)
+    {
+        const int64_t nl = s->E * NP;
+        hipLaunchKernelGGL((k_force_set<T>), dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, s->stream, nodemap(s),
+                           d_F, DIM, static_cast<T *>(s->Fn));
+        SEL_LAUNCH_CHECK();
+        return SEL_OK;
+    }
+
+    // its F** part on the post-collision state f
+    static int force_collide(sel_sim *s, T *f, const float *dtau)
+    {
+        hipLaunchKernelGGL((k_force_collide<DIM, Q, T, DEV>), dim3((unsigned)((s->Gtot + 255) / 256)), dim3(256), 0,
+                           s->stream, f, static_cast<const T *>(s->Fn), dtau, s->Gtot, s->Gi, NI, (int64_t)Q * s->Gi,
+                           T(s->tau), T(s->p.dt), T(s->p.rho0));
+        SEL_LAUNCH_CHECK();
+        return SEL_OK;
+    }
+
+    // its F* part of a stage: out += cc F*(F_n)
+    static int force_stage(sel_sim *s, T *out, double cc)
+    {
+        hipLaunchKernelGGL((k_force_stage<DIM, Q, T>), dim3((unsigned)((s->Gtot + 255) / 256)), dim3(256), 0,
+                           s->stream, out, static_cast<const T *>(s->Fn), s->Gtot, s->Gi, NI, (int64_t)Q * s->Gi,
+                           T(cc));
+        SEL_LAUNCH_CHECK();
+        return SEL_OK;
+    }
+
     // One element pass and its assembly: out = ca f0 + cb fk + cc L(fk).
     static int stage_pass(sel_sim *s, StageArgs<T> &A, GroupArgs<T> &B, const T *fk, const T *f0, T *out,
                           double ca, double cb, double cc)
@@ -185,14 +215,16 @@ struct Impl {
         B.ca = T(ca);
         B.cb = T(cb);
         B.cc = T(cc);
-        return launch_group(s, B);
+        if (int rc = launch_group(s, B)) return rc;
+        return s->force_on ? force_stage(s, out, cc) : SEL_OK;
     }
 
     // First stage: filter (when pending) and collide the state S into the
     // post-collision state y = F0, then FA = y + cc L(y). The continuous
     // coupling streams in the same kernel (a shared node's post-collision
     // value is the same in every element); the discontinuous coupling needs
-    // the post-collision values across faces and streams in a second pass.
+    // the post-collision values across faces, and a per-node force adds its
+    // F** part to y first, so both stream in a second pass.
     static int stage_one(sel_sim *s, StageArgs<T> &A, GroupArgs<T> &B, const T *S, T *F0, T *FA, double cc,
                          bool pending)
     {
@@ -203,11 +235,14 @@ struct Impl {
         A.cb = T(1);
         A.cc = T(cc);
         A.filter = pending ? 1 : 0;
-        if (s->nbr) {
+        if (s->nbr || s->force_on) {
             A.collide_only = 1;
             const int rc = launch_stage<M_STAGE1>(s, A);
             A.collide_only = 0;
             if (rc) return rc;
+            if (s->force_on) {
+                if (int rc2 = force_collide(s, F0, A.dtau)) return rc2;
+            }
             return stage_pass(s, A, B, F0, F0, FA, 0.0, 1.0, cc);
         }
         if (int rc = launch_stage<M_STAGE1>(s, A)) return rc;
@@ -282,32 +317,9 @@ struct Impl {
             // stage 1: f1 = f0 + dt L(f0), f0 = collide(filter(f3_prev) or f-bar)
             if (int rc = stage_one(s, A, B, S, F0, FA, dt, pending)) return rc;
             // stage 2: f2 = 3/4 f0 + 1/4 (f1 + dt L(f1))
-            A.op = FA;
-            A.f0in = F0;
-            A.out = FB;
-            A.ca = T(0.75);
-            A.cb = T(0.25);
-            A.cc = T(0.25 * dt);
-            if (int rc = launch_stage<M_STAGE23>(s, A)) return rc;
-            B.fk = FA;
-            B.out = FB;
-            B.ca = T(0.75);
-            B.cb = T(0.25);
-            B.cc = T(0.25 * dt);
-            if (int rc = launch_group(s, B)) return rc;
+            if (int rc = stage_pass(s, A, B, FA, F0, FB, 0.75, 0.25, 0.25 * dt)) return rc;
             // stage 3: f3 = 1/3 f0 + 2/3 (f2 + dt L(f2)), written over the state
-            A.op = FB;
-            A.out = S;
-            A.ca = T(1.0 / 3.0);
-            A.cb = T(2.0 / 3.0);
-            A.cc = T(2.0 / 3.0 * dt);
-            if (int rc = launch_stage<M_STAGE23>(s, A)) return rc;
-            B.fk = FB;
-            B.out = S;
-            B.ca = T(1.0 / 3.0);
-            B.cb = T(2.0 / 3.0);
-            B.cc = T(2.0 / 3.0 * dt);
-            if (int rc = launch_group(s, B)) return rc;
+            if (int rc = stage_pass(s, A, B, FB, F0, S, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0 * dt)) return rc;
             pending = filt;
             s->time += dt;
             s->nstep += 1;
@@ -430,7 +442,7 @@ struct Impl {
 
     static const Ops *ops()
     {
-        static const Ops o = {geometry, mass, init, step, moments, reduce, scatter, gather, apply, features};
+        static const Ops o = {geometry, mass, init, step, moments, reduce, scatter, gather, apply, features, set_force};
         return &o;
     }
 };

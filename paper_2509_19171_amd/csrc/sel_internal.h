@@ -109,6 +109,8 @@ struct sel_sim {
     int32_t *posmap = nullptr; // [E][nbe] contribution slot
     int32_t *hidx = nullptr;   // [ngrp]
     int32_t *nbr = nullptr;    // discontinuous coupling: [E][2 dim][nfn] group across each face, or nullptr
+    void *Fn = nullptr;        // T [Gtot][3] force density per node id (added to rho g)
+    bool force_on = false;
     int nfn = 0;
     int64_t plane = 0, ngp = 0, nmp = 0;
     void *wallu = nullptr;     // T [ntags+1][3], row 0 = zero

@@ -75,6 +75,7 @@ def load():
         "sel_reduce": [P, P],
         "sel_get_f": [P, P],
         "sel_set_f": [P, P],
+        "sel_set_force": [P, P],
         "sel_get_time": [P, P, P],
         "sel_apply": [P, I32, P, P],
         "sel_geometry": [P, P, P],
@@ -266,6 +267,15 @@ class Sim:
         out = np.zeros(self.dim + 3)
         _check(self._lib.sel_reduce(self._h, _ptr(out)))
         return out
+
+    def set_force(self, F):
+        """Force density per node [E][np][dim] added to rho g from the next
+        step on (sel_set_force); None removes it."""
+        if F is None:
+            _check(self._lib.sel_set_force(self._h, None))
+            return
+        F = np.ascontiguousarray(F, dtype=np.float64).reshape(self.E, self.np_, self.dim)
+        _check(self._lib.sel_set_force(self._h, _ptr(F)))
 
     def get_f(self):
         f = np.zeros((self.E, self.Q, self.np_))
