@@ -81,6 +81,10 @@ def algorithmic_bytes(info, Q, s):
 
 MLP_FLOP_PER_ROW = 2 * (6 * 64 + 64 * 64 * 2 + 64)  # 17280: three hidden layers and the output
 PEAK_FP32_MATRIX_TFLOPS = 157.3
+# training: forward, back-propagated deltas and weight gradient, each a pass
+# of the size of the forward
+TRAIN_FLOP_PER_ROW = 3 * MLP_FLOP_PER_ROW
+PEAK_FP32_VECTOR_TFLOPS = 157.3
 
 
 def time_form(case, precision, steps, warmup, torch, closure=None):
@@ -106,6 +110,35 @@ def time_form(case, precision, steps, warmup, torch, closure=None):
     del sim
     torch.cuda.empty_cache()
     return out
+
+
+def time_training(torch, steps=100, warmup=10, batch=4096, rows=1 << 20):
+    """Adam steps of the closure network on seeded minibatches of a seeded
+    feature set (the recipe of the closure training: minibatches of 4096)."""
+    from paper_2509_19171_amd import inputs as I
+    from paper_2509_19171_amd import sel
+
+    g = torch.Generator(device="cpu").manual_seed(7)
+    X = torch.randn((rows, 6), generator=g).cuda()
+    y = torch.rand((rows,), generator=g).cuda()
+    idx = [torch.randint(0, rows, (batch,), generator=g, dtype=torch.int32).cuda() for _ in range(8)]
+    params = torch.tensor(I.closure_blob(0, mean=[0.0] * 6, std=[1.0] * 6), device="cuda")
+    tr = sel.MLPTrainer(params)
+    for k in range(warmup):
+        tr.step(X, y, idx=idx[k % 8], want_loss=False)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for k in range(steps):
+        tr.step(X, y, idx=idx[k % 8], want_loss=False)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    tflops = TRAIN_FLOP_PER_ROW * batch / (ms * 1e-3) / 1e12
+    return {"minibatch": batch, "ms_per_adam_step": round(ms, 5), "samples_per_s": round(batch / (ms * 1e-3), 1),
+            "bound": "alu", "achieved_TFLOPs": round(tflops, 3), "peak_TFLOPs": PEAK_FP32_VECTOR_TFLOPS,
+            "frac": round(tflops / PEAK_FP32_VECTOR_TFLOPS, 5), "flop_per_sample": TRAIN_FLOP_PER_ROW}
 
 
 def form_summary(f, nv, info, Q, s):
@@ -210,6 +243,8 @@ def main():
         # own face nodes and the elements couple through upwind face fluxes
         print(f"[bench] timing fp32dev+dg: {w} warmup + {k} steps", file=sys.stderr, flush=True)
         forms["fp32dev+dg"] = time_form(dataclasses.replace(case, coupling="dg"), "fp32dev", k, w, torch)
+        print("[bench] timing closure training steps", file=sys.stderr, flush=True)
+        training = time_training(torch)
 
     head = forms[args.precision]
     info = head["info"]
@@ -263,6 +298,8 @@ def main():
         "forms": {p: form_summary(f, nv, info, case.Q, 4 if p.startswith("fp32") else 8) for p, f in forms.items()},
         "src_hash": src_hash(),
     }
+    if not args.no_other_form:
+        result["closure_training"] = training
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(case)

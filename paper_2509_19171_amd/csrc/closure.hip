@@ -178,10 +178,23 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const float *__restrict__ P, 
 
 // ------------------------------------------------------------- training --
 // Work layout (floats): Xn[n][8], H1, H2, H3, D1, D2, D3 [n][64], Z[n], DZ[n],
-// grad[NTRAIN], loss partials [nblk].
+// grad[NTRAIN], loss partials [nblk] and the loss, weight-gradient partials
+// [nchunk][NTRAIN].
 struct TrainWork {
-    float *Xn, *H1, *H2, *H3, *D1, *D2, *D3, *Z, *DZ, *grad, *part;
+    float *Xn, *H1, *H2, *H3, *D1, *D2, *D3, *Z, *DZ, *grad, *part, *wpart;
 };
+
+int64_t train_blocks(int64_t n) { return (n + 255) / 256; }
+
+// The weight gradient sums over the samples in chunks (at least 64 samples,
+// at most 1024 chunks), then over the chunks in order: the result does not
+// depend on the launch, and every chunk is a short loop of its own.
+int64_t wgrad_chunk(int64_t n)
+{
+    const int64_t c = (n + 1023) / 1024;
+    return c < 64 ? 64 : c;
+}
+int64_t wgrad_chunks(int64_t n) { return (n + wgrad_chunk(n) - 1) / wgrad_chunk(n); }
 
 TrainWork carve_work(float *w, int64_t n)
 {
@@ -197,10 +210,9 @@ TrainWork carve_work(float *w, int64_t n)
     t.DZ = t.Z + n;
     t.grad = t.DZ + n;
     t.part = t.grad + NTRAIN;
+    t.wpart = t.part + train_blocks(n) + 1;
     return t;
 }
-
-int64_t train_blocks(int64_t n) { return (n + 255) / 256; }
 
 // dense layer of one sample: out[c] = tanh(b[c] + sum_k W[c][k] in[k]), in registers
 template <int K>
@@ -287,8 +299,9 @@ __global__ void __launch_bounds__(256) k_train_bwd(const float *__restrict__ P, 
     if (threadIdx.x == 0) T.part[blockIdx.x] = red[0];
 }
 
-// one thread per trainable parameter; sums over samples in index order
-__global__ void __launch_bounds__(256) k_train_wgrad(int64_t n, TrainWork T)
+// partial gradients: one thread per trainable parameter and chunk of samples
+// (blockIdx.y, then every gridDim.y-th chunk), summed in sample order
+__global__ void __launch_bounds__(256) k_train_wgrad(int64_t n, int64_t chunk, int64_t nchunk, TrainWork T)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= NTRAIN) return;
@@ -305,11 +318,24 @@ __global__ void __launch_bounds__(256) k_train_wgrad(int64_t n, TrainWork T)
     else if (o < OFF_B4) { D = T.DZ; Aa = T.H3; K = NH; m = 0; k = o - OFF_W4; }
     else { D = T.DZ; Aa = nullptr; K = 0; m = 0; k = 0; bias = true; }
     const int Dstride = (D == T.DZ) ? 1 : NH;
-    float g = 0.f;
-    for (int64_t s = 0; s < n; ++s) {
-        const float dv = D[s * Dstride + m];
-        g += bias ? dv : dv * Aa[s * K + k];
+    for (int64_t c = blockIdx.y; c < nchunk; c += gridDim.y) {
+        const int64_t s1 = (c + 1) * chunk < n ? (c + 1) * chunk : n;
+        float g = 0.f;
+        for (int64_t s = c * chunk; s < s1; ++s) {
+            const float dv = D[s * Dstride + m];
+            g += bias ? dv : dv * Aa[s * K + k];
+        }
+        T.wpart[c * NTRAIN + q] = g;
     }
+}
+
+// the gradient: the partials summed in chunk order
+__global__ void __launch_bounds__(256) k_train_wsum(int64_t nchunk, TrainWork T)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= NTRAIN) return;
+    float g = 0.f;
+    for (int64_t c = 0; c < nchunk; ++c) g += T.wpart[c * NTRAIN + q];
     T.grad[q] = g;
 }
 
@@ -319,6 +345,21 @@ __global__ void k_train_loss(const float *part, int nb, int64_t n, float *out)
     float s = 0.f;
     for (int b = 0; b < nb; ++b) s += part[b];
     out[0] = s / float(n);
+}
+
+// forward, back-propagation, loss and gradient of n samples into T
+void launch_gradient(const float *P, const float *X, const float *y, const int32_t *idx, int64_t n, TrainWork T,
+                     float *dloss, hipStream_t st)
+{
+    const int64_t nb = train_blocks(n);
+    hipLaunchKernelGGL(k_train_fwd, dim3((unsigned)nb), dim3(256), 0, st, P, X, idx, n, T);
+    hipLaunchKernelGGL(k_train_bwd, dim3((unsigned)nb), dim3(256), 0, st, P, y, idx, n, T);
+    hipLaunchKernelGGL(k_train_loss, dim3(1), dim3(64), 0, st, T.part, (int)nb, n, dloss);
+    const unsigned gq = (NTRAIN + 255) / 256;
+    const int64_t nchunk = wgrad_chunks(n);
+    const unsigned gy = (unsigned)(nchunk < 65535 ? nchunk : 65535);
+    hipLaunchKernelGGL(k_train_wgrad, dim3(gq, gy), dim3(256), 0, st, n, wgrad_chunk(n), nchunk, T);
+    hipLaunchKernelGGL(k_train_wsum, dim3(gq), dim3(256), 0, st, nchunk, T);
 }
 
 // Adam (Kingma & Ba), bias-corrected, on the trainable range
@@ -715,7 +756,8 @@ extern "C" int sel_mlp_forward(const float *d_params, const float *d_X, int64_t 
 
 extern "C" int64_t sel_mlp_work_floats(int64_t n)
 {
-    return (8 + 6 * (int64_t)sel::NH + 2) * n + sel::NTRAIN + sel::train_blocks(n) + 1;
+    return (8 + 6 * (int64_t)sel::NH + 2) * n + sel::NTRAIN + sel::train_blocks(n) + 1 +
+           sel::wgrad_chunks(n) * sel::NTRAIN;
 }
 
 extern "C" int sel_mlp_train_step(float *d_params, float *d_m, float *d_v, const float *d_X, const float *d_y,
@@ -728,13 +770,9 @@ extern "C" int sel_mlp_train_step(float *d_params, float *d_m, float *d_v, const
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
     sel::TrainWork T = sel::carve_work(d_work, n);
-    const int64_t nb = sel::train_blocks(n);
-    float *dloss = T.part + nb;
-    hipLaunchKernelGGL(sel::k_train_fwd, dim3((unsigned)nb), dim3(256), 0, st, d_params, d_X, d_idx, n, T);
-    hipLaunchKernelGGL(sel::k_train_bwd, dim3((unsigned)nb), dim3(256), 0, st, d_params, d_y, d_idx, n, T);
-    hipLaunchKernelGGL(sel::k_train_loss, dim3(1), dim3(64), 0, st, T.part, (int)nb, n, dloss);
+    float *dloss = T.part + sel::train_blocks(n);
+    sel::launch_gradient(d_params, d_X, d_y, d_idx, n, T, dloss, st);
     const unsigned gq = (sel::NTRAIN + 255) / 256;
-    hipLaunchKernelGGL(sel::k_train_wgrad, dim3(gq), dim3(256), 0, st, n, T);
     hipLaunchKernelGGL(sel::k_adam, dim3(gq), dim3(256), 0, st, d_params, d_m, d_v, T.grad, t, float(lr), float(b1),
                        float(b2), float(eps));
     if (hipGetLastError() != hipSuccess) {
@@ -762,13 +800,8 @@ extern "C" int sel_mlp_gradient(const float *d_params, const float *d_X, const f
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
     sel::TrainWork T = sel::carve_work(d_work, n);
-    const int64_t nb = sel::train_blocks(n);
-    float *dloss = T.part + nb;
-    hipLaunchKernelGGL(sel::k_train_fwd, dim3((unsigned)nb), dim3(256), 0, st, d_params, d_X, d_idx, n, T);
-    hipLaunchKernelGGL(sel::k_train_bwd, dim3((unsigned)nb), dim3(256), 0, st, d_params, d_y, d_idx, n, T);
-    hipLaunchKernelGGL(sel::k_train_loss, dim3(1), dim3(64), 0, st, T.part, (int)nb, n, dloss);
-    const unsigned gq = (sel::NTRAIN + 255) / 256;
-    hipLaunchKernelGGL(sel::k_train_wgrad, dim3(gq), dim3(256), 0, st, n, T);
+    float *dloss = T.part + sel::train_blocks(n);
+    sel::launch_gradient(d_params, d_X, d_y, d_idx, n, T, dloss, st);
     if (hipMemcpyAsync(d_grad, T.grad, sizeof(float) * sel::NTRAIN, hipMemcpyDeviceToDevice, st) != hipSuccess) {
         set_error("sel_mlp_gradient: copy failed");
         return SEL_EDEVICE;
