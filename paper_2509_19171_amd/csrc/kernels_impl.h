@@ -777,9 +777,17 @@ struct GroupArgs {
     T ca, cb, cc;
     int incr;  // ca + cb = 1 (time steps): FP32 increment form
     T fsc[kMaxQ];
+    // discontinuous coupling (k_group with DGN = N): interface table, face
+    // tags, node index of each boundary slot and the metric
+    const int32_t *nbr, *ftag, *bpos;
+    const T *Gm;
 };
 
-template <int Q, typename T>
+// DGN = 0: continuous coupling. DGN = N: discontinuous coupling at order N,
+// where every group is one element-boundary node (group id e * NB + b) and
+// the upwind flux of its interface faces (interface_flux, with the operand
+// fk across each face) is added to its contribution before the mass.
+template <int Q, typename T, int DGN = 0>
 __global__ void __launch_bounds__(256) k_group(GroupArgs<T> A)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -808,6 +816,36 @@ __global__ void __launch_bounds__(256) k_group(GroupArgs<T> A)
         static_for<0, Q>([&](auto AA) {
             constexpr int a = decltype(AA)::value;
             sum[a] += A.rtb[(int64_t)a * A.plane + o];
+        });
+    }
+    if constexpr (DGN > 0) {
+        constexpr int DIM = (Q == 9) ? 2 : 3;
+        constexpr int n1 = DGN + 1, NP = ipow_c(n1, DIM), NB = NP - ipow_c(DGN - 1, DIM);
+        constexpr int nfn = (DIM == 2) ? n1 : n1 * n1;
+        const int64_t e = g / NB;
+        const int p = A.bpos[g - e * NB];
+        const int i = p % n1, j = (p / n1) % n1, k = (DIM == 3) ? p / (n1 * n1) : 0;
+        uint32_t icode = 0;
+        int32_t gnb[DIM] = {};
+        T Gr[DIM][DIM] = {};
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) {
+            const int idx = (m == 0) ? i : (m == 1) ? j : k;
+            if (idx == 0 || idx == DGN) {
+                const int fc = 2 * m + (idx == DGN ? 1 : 0);
+                if (A.ftag[e * 2 * DIM + fc] == 0) {
+                    const int t0 = (m == 0) ? j : i;
+                    const int t1 = (DIM == 2) ? 0 : (m == 2) ? j : k;
+                    gnb[m] = A.nbr[(e * 2 * DIM + fc) * nfn + t0 + n1 * t1];
+                    icode |= (1u | (idx == DGN ? 2u : 0u)) << (2 * m);
+#pragma unroll
+                    for (int q = 0; q < DIM; ++q) Gr[m][q] = A.Gm[(e * DIM * DIM + m * DIM + q) * NP + p];
+                }
+            }
+        }
+        static_for<0, Q>([&](auto AA) {
+            constexpr int a = decltype(AA)::value;
+            interface_flux<DIM, DGN, Q, a>(sum[a], vk[a], Gr, icode, gnb, A.fk, A.QGi);
         });
     }
     static_for<0, Q>([&](auto AA) {

@@ -85,6 +85,10 @@ struct Impl {
         B.ngp = s->ngp;
         B.nmp = s->nmp;
         for (int a = 0; a < Q; ++a) B.fsc[a] = T(s->fsc[a]);
+        B.nbr = s->nbr;
+        B.ftag = s->ftag;
+        B.bpos = s->bpos;
+        B.Gm = static_cast<const T *>(s->Gm);
         return B;
     }
 
@@ -111,9 +115,12 @@ struct Impl {
         hipEvent_t ev = nullptr;
         const int kind = (MODE == M_STAGE1) ? 0 : (MODE == M_STAGE23) ? 1 : 3;
         if (int rc = tic(s, kind, ev)) return rc;
-        bool dg = false;  // streaming with the discontinuous coupling's interface flux
-        if constexpr (MODE == M_STAGE23 || MODE == M_LOCAL) dg = A.nbr != nullptr;
-        if constexpr (MODE == M_STAGE23 || MODE == M_LOCAL) {
+        // element contributions under the discontinuous coupling carry the
+        // interface flux themselves; in the stages it is added by the
+        // assembly (k_group), where every element-boundary node is a group
+        bool dg = false;
+        if constexpr (MODE == M_LOCAL) {
+            dg = A.nbr != nullptr;
             if (dg) hipLaunchKernelGGL((k_stage<DIM, N, Q, T, DEV, MODE, true>), grid, block, 0, s->stream, A);
         }
         if (!dg) hipLaunchKernelGGL((k_stage<DIM, N, Q, T, DEV, MODE>), grid, block, 0, s->stream, A);
@@ -127,7 +134,9 @@ struct Impl {
         dim3 grid((unsigned)((s->ngrp + 255) / 256)), block(256);
         hipEvent_t ev = nullptr;
         if (int rc = tic(s, 2, ev)) return rc;
-        hipLaunchKernelGGL((k_group<Q, T>), grid, block, 0, s->stream, B);
+        // the discontinuous coupling adds its interface flux here
+        if (B.nbr) hipLaunchKernelGGL((k_group<Q, T, N>), grid, block, 0, s->stream, B);
+        else hipLaunchKernelGGL((k_group<Q, T>), grid, block, 0, s->stream, B);
         SEL_LAUNCH_CHECK();
         return toc(s, ev);
     }
