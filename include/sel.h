@@ -181,6 +181,13 @@ int sel_set_f(sel_sim *sim, const double *f);
  * SEL_EINVAL (null sim or a non-finite entry). Synchronises. */
 int sel_set_force(sel_sim *sim, const double *F);
 
+/* Velocity gradient of the current state at every element node:
+ * grad [E][np][dim][dim] (FP64 host), grad[..][c][q] = du_c/dx_q, from the
+ * element-local derivative with the metric of Sec. 2.2 (u = sum e f / rho,
+ * Eq. momentum). Gives the wall shear stress of Sec. 3.5 and the dissipation
+ * rate of Sec. 3.4. Synchronises. */
+int sel_velocity_gradient(sel_sim *sim, double *grad);
+
 /* Simulated time and step count. */
 int sel_get_time(const sel_sim *sim, double *t, int64_t *nstep);
 

@@ -149,6 +149,17 @@ def _grad_nodal(sim, fieldE):
     return np.einsum("epmk,mep->epk", drdx, np.stack(dref))
 
 
+def velocity_gradient(sim, f=None):
+    """du_c/dx_q [E][np][dim][dim] of the state f (default: the oracle's
+    state), element-local derivative with the metric (Sec. 2.2)."""
+    dim, Q = sim.dim, sim.Q
+    if f is None:
+        f = sim.get_f()
+    e, _, _ = lattice(dim, Q)
+    u = np.einsum("eap,ak->epk", f, e) / f.sum(1)[..., None]
+    return np.stack([_grad_nodal(sim, u[..., i]) for i in range(dim)], axis=2)
+
+
 def features(sim, f=None):
     """Features [E][np][6] of the state f (default: the oracle's state)."""
     dim, Q = sim.dim, sim.Q

@@ -548,6 +548,25 @@ extern "C" int sel_set_force(sel_sim *s, const double *F)
     return sync_check(s);
 }
 
+extern "C" int sel_velocity_gradient(sel_sim *s, double *grad)
+{
+    if (!s || !grad) {
+        set_error("sel_velocity_gradient: null argument");
+        return SEL_EINVAL;
+    }
+    const int64_t nl = s->E * (int64_t)s->np;
+    const int d = s->dim;
+    std::vector<double> row((size_t)nl * d);
+    for (int c = 0; c < d; ++c) {
+        if (int rc = ops_of(s)->grad_row(s, c, s->io)) return rc;
+        HIP_OK(hipMemcpyAsync(row.data(), s->io, 8 * row.size(), hipMemcpyDeviceToHost, s->stream));
+        HIP_OK(hipStreamSynchronize(s->stream));
+        for (int64_t l = 0; l < nl; ++l)
+            for (int q = 0; q < d; ++q) grad[(l * d + c) * d + q] = row[l * d + q];
+    }
+    return sync_check(s);
+}
+
 extern "C" int sel_get_time(const sel_sim *s, double *t, int64_t *nstep)
 {
     if (!s) {

@@ -875,6 +875,8 @@ struct FeatArgs {
     T rho0, lam;
     int owner_out;
     int filter;  // features of the filtered state (the filter is linear, so the moment fields are filtered)
+    double *grad;  // when set: row grad_row of the velocity gradient, du_c/dx_q [E][np][dim] (FP64), no features
+    int grad_row;
 };
 
 template <int DIM, int N, int Q, typename T, bool DEV>
@@ -1011,6 +1013,17 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_features(FeatArgs<T> A
 #pragma unroll
             for (int c = 0; c < DIM; ++c) Am[c][q] += du[c][m] * drdx;
         }
+    if (A.grad) {
+#pragma unroll
+        for (int q = 0; q < DIM; ++q) {
+            T v = 0;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c)
+                if (c == A.grad_row) v = Am[c][q];
+            A.grad[(e * NP + p) * DIM + q] = double(v);
+        }
+        return;
+    }
     T S[3][3], W[3][3];
 #pragma unroll
     for (int r = 0; r < 3; ++r)

@@ -424,9 +424,17 @@ struct Impl {
 
     // closure features of the current state: one row per node id
     // (owner_out = 1) or per element node
-    static int features(sel_sim *s, float *X, int owner_out, int filter)
+    static int features(sel_sim *s, float *X, int owner_out, int filter) { return feat(s, X, owner_out, filter, nullptr, 0); }
+
+    // row c of the velocity gradient of the current state, du_c/dx_q per
+    // element node [E][np][dim] (FP64, device)
+    static int grad_row(sel_sim *s, int c, double *d_out) { return feat(s, nullptr, 0, 0, d_out, c); }
+
+    static int feat(sel_sim *s, float *X, int owner_out, int filter, double *grad, int row)
     {
         FeatArgs<T> F{};
+        F.grad = grad;
+        F.grad_row = row;
         F.f = st(s, s->cur);
         F.F = static_cast<const T *>(s->tabF);
         F.filter = filter;
@@ -451,7 +459,8 @@ struct Impl {
 
     static const Ops *ops()
     {
-        static const Ops o = {geometry, mass, init, step, moments, reduce, scatter, gather, apply, features, set_force};
+        static const Ops o = {geometry, mass, init,    step,     moments,  reduce,   scatter,
+                              gather,   apply, features, set_force, grad_row};
         return &o;
     }
 };

@@ -541,13 +541,61 @@ def pipe_perturbation(xyz, R, L, amp, seed=180, nmodes=16, scale=None):
     return u * (amp / m if m > 0 else 0.0)
 
 
+def law_of_wall(yplus, kappa=0.41, Cplus=5.0):
+    """Mean streamwise velocity in wall units (Sec. 3.5): u+ = y+ in the
+    viscous sublayer and ln(y+)/kappa + C+ in the inertial sublayer, switched
+    where the two meet (y+ = 11.4 for kappa = 0.41, C+ = 5), so that the
+    profile is continuous."""
+    yplus = np.asarray(yplus, dtype=np.float64)
+    # crossing of y+ and ln(y+)/kappa + C+ above y+ = 1 (bisection)
+    lo, hi = 1.0, 100.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if mid < math.log(mid) / kappa + Cplus:
+            lo = mid
+        else:
+            hi = mid
+    yc = 0.5 * (lo + hi)
+    inertial = np.log(np.maximum(yplus, 1e-300)) / kappa + Cplus
+    return np.where(yplus < yc, yplus, inertial)
+
+
+def pipe_force(xyz, t, R, L, g, t0, kz=3, ktheta=4, B0=50.0, kappa=0.5, period=8.0, l0=0.2, lw=0.4):
+    """Divergence-free perturbation force of the pipe case (Sec. 3.5): in
+    cylindrical components, with S = sin(2 pi t / P), phi = 2 pi (R - r - l0)/l,
+    Z = 2 pi k_z z / L and the region l0 <= R - r <= l0 + l (zero elsewhere),
+      F_r = -g kappa B0 (R/r) (k_z l / L) S (1 - cos phi) cos Z cos(k_t theta),
+      F_t = g (1 - kappa) B0 (k_z / k_t) (2 pi R / L) S sin phi cos Z sin(k_t theta),
+      F_z = -g B0 (R/r) S sin phi sin Z cos(k_t theta),
+    returned in Cartesian components [E][np][3] (per unit density). P is
+    period * t0, l0 = l0 R, l = lw R. The paper leaves the wavenumbers k_z
+    and k_theta open; they are parameters here. It applies the field for
+    t < 3 t0."""
+    x, y, z = xyz[..., 0], xyz[..., 1], xyz[..., 2]
+    r = np.sqrt(x * x + y * y)
+    th = np.arctan2(y, x)
+    l0, l = l0 * R, lw * R
+    inside = (R - r >= l0) & (R - r <= l0 + l)
+    rs = np.where(inside, r, R)  # the region keeps r >= R - l0 - l > 0
+    S = math.sin(2 * math.pi * t / (period * t0))
+    ph = 2 * math.pi * (R - rs - l0) / l
+    Zc, Zs = np.cos(kz * 2 * math.pi * z / L), np.sin(kz * 2 * math.pi * z / L)
+    Fr = -g * kappa * B0 * (R / rs) * (kz * l / L) * S * (1 - np.cos(ph)) * Zc * np.cos(ktheta * th)
+    Ft = g * (1 - kappa) * B0 * (kz / ktheta) * (2 * math.pi * R / L) * S * np.sin(ph) * Zc * np.sin(ktheta * th)
+    Fz = -g * B0 * (R / rs) * S * np.sin(ph) * Zs * np.cos(ktheta * th)
+    F = np.stack([Fr * np.cos(th) - Ft * np.sin(th), Fr * np.sin(th) + Ft * np.cos(th), Fz], axis=-1)
+    return np.where(inside[..., None], F, 0.0)
+
+
 def case_pipe(N=7, nsq=8, nrad=8, nax=64, R=1.0, L=10.0, Re_tau=180.0, Ma=0.1, pert=0.05, seed=180,
-              steps=200, filt="exp", cfl=0.5) -> Case:
+              steps=200, filt="exp", cfl=0.5, init="parabolic") -> Case:
     """Turbulent pipe flow: O-grid, FBB wall at rest, body acceleration
-    g = 2 u_tau^2 / R along z, initial u_z = 2 u_b (1 - r^2/R^2) plus a seeded
-    divergence-free perturbation of pert * u_b. u_b = Ma c_s,
-    u_tau = u_b / 14.7 (the bulk-to-friction ratio at Re_tau = 180),
-    nu = u_tau R / Re_tau."""
+    g = 2 u_tau^2 / R along z. u_b = Ma c_s, u_tau = u_b / 14.7 (the
+    bulk-to-friction ratio at Re_tau = 180), nu = u_tau R / Re_tau. Initial
+    u_z: init "parabolic", 2 u_b (1 - r^2/R^2), or "law_of_wall", u_tau u+(y+)
+    with y+ = (R - r) u_tau / nu (Sec. 3.5); plus a seeded divergence-free
+    perturbation of pert * u_b. The perturbation force of Sec. 3.5 is
+    pipe_force, set per node by the caller."""
     mesh = pipe_mesh(N, nsq, nrad, nax, R, L)
     ub = Ma * CS
     utau = ub / 14.7
@@ -557,8 +605,14 @@ def case_pipe(N=7, nsq=8, nrad=8, nax=64, R=1.0, L=10.0, Re_tau=180.0, Ma=0.1, p
     x = mesh.xyz
     r2 = (x[..., 0] ** 2 + x[..., 1] ** 2) / (R * R)
     u = np.zeros(x.shape)
-    u[..., 2] = 2.0 * ub * np.maximum(0.0, 1.0 - r2)
+    if init == "parabolic":
+        u[..., 2] = 2.0 * ub * np.maximum(0.0, 1.0 - r2)
+    elif init == "law_of_wall":
+        yplus = np.maximum(R - np.sqrt(r2) * R, 0.0) * utau / nu
+        u[..., 2] = utau * law_of_wall(yplus)
+    else:
+        raise ValueError(init)
     u += pipe_perturbation(x, R, L, pert * ub, seed=seed)
     rho = np.ones(x.shape[:2])
     return Case("pipe", mesh, 27, 1.0, nu, dt, rho, u, steps, g=(0.0, 0.0, g),
-                meta=dict(R=R, L=L, ub=ub, utau=utau, Re_tau=Re_tau), **_filter_kw(filt, N))
+                meta=dict(R=R, L=L, ub=ub, utau=utau, Re_tau=Re_tau, g=g, t0=R / utau), **_filter_kw(filt, N))

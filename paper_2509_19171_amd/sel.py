@@ -76,6 +76,7 @@ def load():
         "sel_get_f": [P, P],
         "sel_set_f": [P, P],
         "sel_set_force": [P, P],
+        "sel_velocity_gradient": [P, P],
         "sel_get_time": [P, P, P],
         "sel_apply": [P, I32, P, P],
         "sel_geometry": [P, P, P],
@@ -266,6 +267,12 @@ class Sim:
     def reduce(self):
         out = np.zeros(self.dim + 3)
         _check(self._lib.sel_reduce(self._h, _ptr(out)))
+        return out
+
+    def velocity_gradient(self):
+        """du_c/dx_q of the current state at every element node [E][np][dim][dim]."""
+        out = np.zeros((self.E, self.np_, self.dim, self.dim))
+        _check(self._lib.sel_velocity_gradient(self._h, _ptr(out)))
         return out
 
     def set_force(self, F):

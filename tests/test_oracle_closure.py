@@ -303,3 +303,18 @@ def test_closure_with_nan_weights_is_plain(oracle_mod, C):
     p.step(4)
     C.step_with_closure(q, prm, 4)
     np.testing.assert_array_equal(p.get_f(), q.get_f())
+
+
+@pytest.mark.parametrize("dim,Q", [(2, 9), (3, 19)])
+def test_velocity_gradient_linear_flow(oracle_mod, C, dim, Q):
+    """The velocity gradient of u = A x + b on a curved mesh is A exactly at
+    every node (isoparametric elements reproduce linear fields)."""
+    N = 4 if dim == 3 else 5
+    mesh = I.box_mesh(dim, N, (2,) * dim, (0,) * dim, (1,) * dim, (False,) * dim,
+                      wall_tags={m: (0, 0) for m in range(dim)}, warp=_warp(dim))
+    sim = oracle_mod.OracleSim(dim, N, mesh.xyz, mesh.gid, mesh.face_tag, mesh.wall_u, Q, 1.0, 0.02, 0.01)
+    A = (np.array([[0.3, 0.7, 0.1], [-0.2, -0.1, 0.4], [0.25, -0.5, -0.2]]) * 0.05)[:dim, :dim]
+    u = mesh.xyz @ A.T + 0.01
+    rho = 1.0 + 0.02 * np.sin(3 * mesh.xyz[..., 0])
+    G = C.velocity_gradient(sim, _feq(oracle_mod, dim, Q, rho, u))
+    np.testing.assert_allclose(G, np.broadcast_to(A, G.shape), rtol=0, atol=1e-12)

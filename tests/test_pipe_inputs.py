@@ -110,3 +110,50 @@ def test_pipe_rest_state_steady(oracle_mod):
     f0 = s.get_f()
     s.step(5)
     assert np.abs(s.get_f() - f0).max() < 1e-14
+
+
+def test_pipe_force_divergence_free():
+    """The perturbation force of the pipe case is divergence-free inside its
+    radial band (central differences, Cartesian components), vanishes outside
+    it and at t = 0, and is periodic along the pipe."""
+    R, L, g, t0 = 1.0, 10.0, 1e-4, 200.0
+    rng = np.random.Generator(np.random.PCG64(5))
+    M = 400
+    rr = R - (0.2 + 0.4 * rng.uniform(0.02, 0.98, M)) * R
+    th = rng.uniform(-np.pi, np.pi, M)
+    z = rng.uniform(0, L, M)
+    p = np.stack([rr * np.cos(th), rr * np.sin(th), z], -1)[:, None, :]
+    t = 0.3 * 8 * t0
+    h = 1e-5
+    div = np.zeros(M)
+    scale = 0.0
+    for k in range(3):
+        dp = np.zeros(3)
+        dp[k] = h
+        d = (I.pipe_force(p + dp, t, R, L, g, t0) - I.pipe_force(p - dp, t, R, L, g, t0))[:, 0, k] / (2 * h)
+        div += d
+        scale = max(scale, np.abs(d).max())
+    assert scale > 0
+    assert np.abs(div).max() < 1e-6 * scale
+    F = I.pipe_force(p, t, R, L, g, t0)
+    assert np.abs(F).max() > 0
+    assert np.abs(I.pipe_force(p, 0.0, R, L, g, t0)).max() == 0.0
+    np.testing.assert_allclose(I.pipe_force(p + np.array([0, 0, L]), t, R, L, g, t0), F, atol=1e-12 * np.abs(F).max())
+    core = np.stack([0.1 * np.cos(th), 0.1 * np.sin(th), z], -1)[:, None, :]
+    wall = np.stack([0.95 * np.cos(th), 0.95 * np.sin(th), z], -1)[:, None, :]
+    assert np.abs(I.pipe_force(core, t, R, L, g, t0)).max() == 0.0
+    assert np.abs(I.pipe_force(wall, t, R, L, g, t0)).max() == 0.0
+
+
+def test_law_of_wall_profile():
+    yp = np.array([0.5, 1.0, 5.0, 10.0, 30.0, 100.0, 180.0])
+    up = I.law_of_wall(yp)
+    np.testing.assert_allclose(up[:4], yp[:4])
+    np.testing.assert_allclose(up[4:], np.log(yp[4:]) / 0.41 + 5.0)
+    # continuous where the two laws meet
+    ys = np.linspace(10.0, 13.0, 3001)
+    assert np.abs(np.diff(I.law_of_wall(ys))).max() < 1e-2
+    c = I.case_pipe(N=3, nsq=2, nrad=2, nax=4, init="law_of_wall", pert=0.0)
+    r = np.hypot(c.mesh.xyz[..., 0], c.mesh.xyz[..., 1])
+    assert np.abs(c.u[..., 2][r > 0.999]).max() < 1e-12  # zero at the wall
+    assert c.u[..., 2].max() > c.meta["ub"]
