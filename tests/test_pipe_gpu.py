@@ -113,3 +113,33 @@ def test_pipe_coarse_closure_run():
         er, eu = nerr(rho, orho), uerr(u, ou)
         say(f"  rho {er:.2e} u {eu:.2e}")
         assert er < tol and eu < tol
+
+
+@pytest.mark.parametrize("prec,steps,tol", [("fp64", 40, 1e-12), ("fp32dev", 200, 1e-5)])
+def test_pipe_forced_law_of_wall(prec, steps, tol):
+    """The paper's start of the pipe run (Sec. 3.5): law-of-the-wall initial
+    profile and the time-dependent divergence-free perturbation force,
+    re-set every 5 steps on both sides (sel_set_force), against the oracle."""
+    import oracle
+    from paper_2509_19171_amd import inputs as I
+    from paper_2509_19171_amd import sel
+
+    c = I.case_pipe(N=5, nsq=2, nrad=2, nax=4, L=2.0, init="law_of_wall", pert=0.0)
+    m = c.meta
+    g = sel.from_case(c, prec)
+    o = oracle.from_case(c)
+    t = 0.0
+    t0 = steps * c.dt / 4  # short time scale: the forcing period 8 t0 spans the run twice over
+    for k in range(steps // 5):
+        F = c.rho0 * I.pipe_force(c.mesh.xyz, t, m["R"], m["L"], m["g"], t0, kz=1, ktheta=2)
+        g.set_force(F)
+        o.set_force(F)
+        g.step(5)
+        o.step(5)
+        t += 5 * c.dt
+    rho, u = g.moments()
+    orho, ou = o.moments()
+    er = np.abs(rho - orho).max() / np.abs(orho).max()
+    eu = np.abs(u - ou).max() / max(np.abs(ou).max(), 0.01)
+    print(f"[gpu]   pipe forced {prec}: rho {er:.2e} u {eu:.2e}", flush=True)
+    assert er < tol and eu < tol
