@@ -879,7 +879,9 @@ struct FeatArgs {
     int grad_row;
 };
 
-template <int DIM, int N, int Q, typename T, bool DEV>
+// GRAD: write one row of the velocity gradient instead of the features (a
+// separate instantiation, so the feature kernel carries none of it)
+template <int DIM, int N, int Q, typename T, bool DEV, bool GRAD = false>
 __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_features(FeatArgs<T> A)
 {
     using GG = Geo<DIM, N>;
@@ -1013,7 +1015,7 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_features(FeatArgs<T> A
 #pragma unroll
             for (int c = 0; c < DIM; ++c) Am[c][q] += du[c][m] * drdx;
         }
-    if (A.grad) {
+    if constexpr (GRAD) {
 #pragma unroll
         for (int q = 0; q < DIM; ++q) {
             T v = 0;

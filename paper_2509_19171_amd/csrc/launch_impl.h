@@ -121,9 +121,13 @@ struct Impl {
         bool dg = false;
         if constexpr (MODE == M_LOCAL) {
             dg = A.nbr != nullptr;
-            if (dg) hipLaunchKernelGGL((k_stage<DIM, N, Q, T, DEV, MODE, true>), grid, block, 0, s->stream, A);
+            if (dg) {
+                hipLaunchKernelGGL((k_stage<DIM, N, Q, T, DEV, MODE, true>), grid, block, 0, s->stream, A);
+            }
         }
-        if (!dg) hipLaunchKernelGGL((k_stage<DIM, N, Q, T, DEV, MODE>), grid, block, 0, s->stream, A);
+        if (!dg) {
+            hipLaunchKernelGGL((k_stage<DIM, N, Q, T, DEV, MODE>), grid, block, 0, s->stream, A);
+        }
         SEL_LAUNCH_CHECK();
         return toc(s, ev);
     }
@@ -135,8 +139,11 @@ struct Impl {
         hipEvent_t ev = nullptr;
         if (int rc = tic(s, 2, ev)) return rc;
         // the discontinuous coupling adds its interface flux here
-        if (B.nbr) hipLaunchKernelGGL((k_group<Q, T, N>), grid, block, 0, s->stream, B);
-        else hipLaunchKernelGGL((k_group<Q, T>), grid, block, 0, s->stream, B);
+        if (B.nbr) {
+            hipLaunchKernelGGL((k_group<Q, T, N>), grid, block, 0, s->stream, B);
+        } else {
+            hipLaunchKernelGGL((k_group<Q, T>), grid, block, 0, s->stream, B);
+        }
         SEL_LAUNCH_CHECK();
         return toc(s, ev);
     }
@@ -452,7 +459,13 @@ struct Impl {
         F.rho0 = T(s->p.rho0);
         F.lam = T(s->p.nu * 3.0);
         F.owner_out = owner_out;
-        hipLaunchKernelGGL((k_features<DIM, N, Q, T, DEV>), dim3((unsigned)F.nblk), dim3(GG::BLOCK), 0, s->stream, F);
+        if (grad) {
+            hipLaunchKernelGGL((k_features<DIM, N, Q, T, DEV, true>), dim3((unsigned)F.nblk), dim3(GG::BLOCK), 0,
+                               s->stream, F);
+        } else {
+            hipLaunchKernelGGL((k_features<DIM, N, Q, T, DEV>), dim3((unsigned)F.nblk), dim3(GG::BLOCK), 0, s->stream,
+                               F);
+        }
         SEL_LAUNCH_CHECK();
         return SEL_OK;
     }
