@@ -41,6 +41,14 @@ __device__ __forceinline__ float guard_dtau(float d, float tau, float dmax)
     return (d == d && d >= 0.f && d <= dmax * tau) ? d : 0.f;
 }
 
+// Work layout (floats): Xn[n][8], H1, H2, H3, D1, D2, D3 [n][64], Z[n], DZ[n],
+// grad[NTRAIN], loss partials [nblk] and the loss, weight-gradient partials
+// [nchunk][NTRAIN].
+struct TrainWork {
+    float *Xn, *H1, *H2, *H3, *D1, *D2, *D3, *Z, *DZ, *grad, *part, *wpart;
+};
+
+
 // ------------------------------------------------------------ inference --
 // One workgroup of 4 wavefronts; each wavefront runs a tile of RW = 32 rows
 // through 6 -> 64 -> 64 -> 64 -> 1 with v_mfma_f32_16x16x4f32 for the three
@@ -53,9 +61,13 @@ __device__ __forceinline__ float guard_dtau(float d, float tau, float dmax)
 constexpr int RW = 32;  // rows per wavefront
 constexpr int RT = RW / 16;
 
-__global__ void __launch_bounds__(256) k_mlp_infer(const float *__restrict__ P, const float *__restrict__ X,
-                                                   int64_t n, float tau, float *__restrict__ zout,
-                                                   float *__restrict__ dtau)
+// TRAIN: the forward pass of a training step on rows idx[s] of X (all rows
+// when idx is null): the normalised inputs, the three hidden layers and z of
+// sample s are stored in T for the back-propagation.
+template <bool TRAIN>
+__global__ void __launch_bounds__(256) k_mlp(const float *__restrict__ P, const float *__restrict__ X,
+                                             const int32_t *__restrict__ idx, int64_t n, float tau,
+                                             float *__restrict__ zout, float *__restrict__ dtau, TrainWork T)
 {
     __shared__ float sW1[NH][9];
     __shared__ float sW2[NH][NH + 1];
@@ -91,10 +103,25 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const float *__restrict__ P, 
         {
             const int rr = l % RW, c0 = 4 * (l / RW);
             const int64_t r = base + w * RW + rr;
+            const int64_t row = (TRAIN && idx && r < n) ? (int64_t)idx[r] : r;
 #pragma unroll
-            for (int c = c0; c < c0 + 4; ++c) sH[w][rr][c] = (c < NF && r < n) ? (X[r * NF + c] - smean[c]) * sistd[c] : 0.f;
+            for (int c = c0; c < c0 + 4; ++c) {
+                const float x = (c < NF && r < n) ? (X[row * NF + c] - smean[c]) * sistd[c] : 0.f;
+                sH[w][rr][c] = x;
+                if (TRAIN && r < n) T.Xn[r * 8 + c] = x;
+            }
         }
         __builtin_amdgcn_wave_barrier();
+        // training: the hidden layer just written to sH, stored row by row
+        auto store_layer = [&](float *H) {
+            if constexpr (TRAIN) {
+                for (int q = l; q < RW * NH; q += 64) {
+                    const int rr = q / NH, c = q - rr * NH;
+                    const int64_t r = base + w * RW + rr;
+                    if (r < n) H[r * NH + c] = sH[w][rr][c];
+                }
+            }
+        };
         f4 acc[RT][4];
         // hidden layer 1 (K = 8)
 #pragma unroll
@@ -125,6 +152,7 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const float *__restrict__ P, 
                     sH[w][16 * ti + 4 * lk + q][col] = tanh_fast(acc[ti][tj][q] + sb1[col]);
                 }
         __builtin_amdgcn_wave_barrier();
+        store_layer(T.H1);
         // hidden layers 2 and 3 (K = 64)
 #pragma unroll
         for (int layer = 0; layer < 2; ++layer) {
@@ -157,6 +185,7 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const float *__restrict__ P, 
                         sH[w][16 * ti + 4 * lk + q][col] = tanh_fast(acc[ti][tj][q] + bl[col]);
                     }
             __builtin_amdgcn_wave_barrier();
+            store_layer(layer == 0 ? T.H2 : T.H3);
         }
         // output layer: two lanes per row, halves of the 64 products
         {
@@ -168,6 +197,7 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const float *__restrict__ P, 
             z += b4;
             const int64_t r = base + w * RW + rr;
             if (h == 0 && r < n) {
+                if constexpr (TRAIN) T.Z[r] = z;
                 if (zout) zout[r] = z;
                 if (dtau) dtau[r] = guard_dtau(tau * softplusf(z), tau, dmax);
             }
@@ -177,13 +207,6 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const float *__restrict__ P, 
 }
 
 // ------------------------------------------------------------- training --
-// Work layout (floats): Xn[n][8], H1, H2, H3, D1, D2, D3 [n][64], Z[n], DZ[n],
-// grad[NTRAIN], loss partials [nblk] and the loss, weight-gradient partials
-// [nchunk][NTRAIN].
-struct TrainWork {
-    float *Xn, *H1, *H2, *H3, *D1, *D2, *D3, *Z, *DZ, *grad, *part, *wpart;
-};
-
 int64_t train_blocks(int64_t n) { return (n + 255) / 256; }
 
 // The weight gradient sums over the samples in chunks (at least 64 samples,
@@ -212,45 +235,6 @@ TrainWork carve_work(float *w, int64_t n)
     t.part = t.grad + NTRAIN;
     t.wpart = t.part + train_blocks(n) + 1;
     return t;
-}
-
-// dense layer of one sample: out[c] = tanh(b[c] + sum_k W[c][k] in[k]), in registers
-template <int K>
-__device__ __forceinline__ void dense_tanh(const float *__restrict__ W, const float *__restrict__ b, const float (&in)[K],
-                                           float *__restrict__ out_row)
-{
-    for (int c = 0; c < NH; ++c) {
-        float s = b[c];
-#pragma unroll
-        for (int k = 0; k < K; ++k) s += W[c * K + k] * in[k];
-        out_row[c] = tanhf(s);
-    }
-}
-
-__global__ void __launch_bounds__(256) k_train_fwd(const float *__restrict__ P, const float *__restrict__ X,
-                                                   const int32_t *__restrict__ idx, int64_t n, TrainWork T)
-{
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const int64_t row = idx ? (int64_t)idx[s] : s;
-    float x[NF];
-#pragma unroll
-    for (int c = 0; c < NF; ++c) {
-        x[c] = (X[row * NF + c] - P[OFF_MEAN + c]) / P[OFF_STD + c];
-        T.Xn[s * 8 + c] = x[c];
-    }
-    dense_tanh<NF>(P + OFF_W1, P + OFF_B1, x, T.H1 + s * NH);
-    float h[NH];
-#pragma unroll
-    for (int c = 0; c < NH; ++c) h[c] = T.H1[s * NH + c];
-    dense_tanh<NH>(P + OFF_W2, P + OFF_B2, h, T.H2 + s * NH);
-#pragma unroll
-    for (int c = 0; c < NH; ++c) h[c] = T.H2[s * NH + c];
-    dense_tanh<NH>(P + OFF_W3, P + OFF_B3, h, T.H3 + s * NH);
-    float z = P[OFF_B4];
-#pragma unroll
-    for (int c = 0; c < NH; ++c) z += P[OFF_W4 + c] * T.H3[s * NH + c];
-    T.Z[s] = z;
 }
 
 // back-propagation of the mean squared error of softplus(z) against y
@@ -352,7 +336,9 @@ void launch_gradient(const float *P, const float *X, const float *y, const int32
                      float *dloss, hipStream_t st)
 {
     const int64_t nb = train_blocks(n);
-    hipLaunchKernelGGL(k_train_fwd, dim3((unsigned)nb), dim3(256), 0, st, P, X, idx, n, T);
+    int64_t nbf = (n + 4 * RW - 1) / (4 * RW);
+    if (nbf > 4096) nbf = 4096;
+    hipLaunchKernelGGL(k_mlp<true>, dim3((unsigned)nbf), dim3(256), 0, st, P, X, idx, n, 1.f, nullptr, nullptr, T);
     hipLaunchKernelGGL(k_train_bwd, dim3((unsigned)nb), dim3(256), 0, st, P, y, idx, n, T);
     hipLaunchKernelGGL(k_train_loss, dim3(1), dim3(64), 0, st, T.part, (int)nb, n, dloss);
     const unsigned gq = (NTRAIN + 255) / 256;
@@ -616,8 +602,8 @@ int launch_mlp_infer(sel_sim *s)
     const int64_t n = s->Gtot;
     int64_t nb = (n + 4 * RW - 1) / (4 * RW);
     if (nb > 4096) nb = 4096;
-    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)nb), dim3(256), 0, s->stream, s->cl_params, s->cl_X, n,
-                       float(s->tau), nullptr, s->cl_dtau);
+    hipLaunchKernelGGL(k_mlp<false>, dim3((unsigned)nb), dim3(256), 0, s->stream, s->cl_params, s->cl_X, nullptr, n,
+                       float(s->tau), nullptr, s->cl_dtau, TrainWork{});
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) {
         set_error(std::string("closure inference launch failed: ") + hipGetErrorString(err));
@@ -745,8 +731,8 @@ extern "C" int sel_mlp_forward(const float *d_params, const float *d_X, int64_t 
     if (n == 0) return SEL_OK;
     int64_t nb = (n + 4 * sel::RW - 1) / (4 * sel::RW);
     if (nb > 4096) nb = 4096;
-    hipLaunchKernelGGL(sel::k_mlp_infer, dim3((unsigned)nb), dim3(256), 0, static_cast<hipStream_t>(stream), d_params,
-                       d_X, n, float(tau), d_z, d_dtau);
+    hipLaunchKernelGGL(sel::k_mlp<false>, dim3((unsigned)nb), dim3(256), 0, static_cast<hipStream_t>(stream), d_params,
+                       d_X, nullptr, n, float(tau), d_z, d_dtau, sel::TrainWork{});
     if (hipGetLastError() != hipSuccess) {
         set_error("sel_mlp_forward: launch failed");
         return SEL_EDEVICE;
