@@ -228,6 +228,9 @@ __device__ __forceinline__ T stream_volume(const T *P, T v, const T (&Di)[N + 1]
 {
     constexpr int n1 = N + 1;
     constexpr int ex = lat_e<DIM, Q>(a, 0), ey = lat_e<DIM, Q>(a, 1), ez = lat_e<DIM, Q>(a, 2);
+    // the rest velocity does not stream (e = 0); without this the products
+    // 0 * (derivative) would still be evaluated
+    if constexpr (ex == 0 && ey == 0 && ez == 0) return T(0);
     T dr = 0, ds = 0, dtt = 0;
     if constexpr (DIF) {
 #pragma unroll
