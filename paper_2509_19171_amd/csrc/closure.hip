@@ -237,50 +237,112 @@ TrainWork carve_work(float *w, int64_t n)
     return t;
 }
 
-// back-propagation of the mean squared error of softplus(z) against y
+// Back-propagation of the mean squared error of softplus(z) against y, on
+// the tiles of k_mlp: each wavefront takes RW rows; the deltas of a layer
+// are formed in its private LDS buffer, D_l = (D_{l+1} W_{l+1}) (1 - H_l^2)
+// with v_mfma_f32_16x16x4f32 (A = deltas, B = W), and stored row by row.
+// dz = (2/n) (softplus(z) - y) sigmoid(z); D3 = dz w4 (1 - H3^2). One loss
+// partial (sum of squared residuals) per workgroup.
 __global__ void __launch_bounds__(256) k_train_bwd(const float *__restrict__ P, const float *__restrict__ y,
                                                    const int32_t *__restrict__ idx, int64_t n, TrainWork T)
 {
+    __shared__ float sW2[NH][NH + 1];
+    __shared__ float sW3[NH][NH + 1];
+    __shared__ float sw4[NH];
+    __shared__ float sH[4][RW][NH + 1];
+    __shared__ float sdz[4][RW];
     __shared__ float red[256];
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int tid = threadIdx.x;
+    for (int q = tid; q < NH * NH; q += 256) {
+        sW2[q / NH][q % NH] = P[OFF_W2 + q];
+        sW3[q / NH][q % NH] = P[OFF_W3 + q];
+    }
+    if (tid < NH) sw4[tid] = P[OFF_W4 + tid];
+    __syncthreads();
+    const int w = tid / 64, l = tid % 64;
+    const int li = l & 15, lk = l >> 4;
+    const float two_n = 2.f / float(n);
     float r2 = 0.f;
-    if (s < n) {
-        const float z = T.Z[s];
-        const float r = softplusf(z) - y[idx ? (int64_t)idx[s] : s];
-        r2 = r * r;
-        const float dz = (2.f / float(n)) * r / (1.f + expf(-z));
-        T.DZ[s] = dz;
-        float d[NH];
-#pragma unroll
-        for (int c = 0; c < NH; ++c) {
-            const float h = T.H3[s * NH + c];
-            d[c] = dz * P[OFF_W4 + c] * (1.f - h * h);
-            T.D3[s * NH + c] = d[c];
+    for (int64_t base = (int64_t)blockIdx.x * (4 * RW); base < n; base += (int64_t)gridDim.x * (4 * RW)) {
+        // residual and dz of the wavefront's rows
+        if (l < RW) {
+            const int64_t r = base + w * RW + l;
+            float dz = 0.f;
+            if (r < n) {
+                const float z = T.Z[r];
+                const float res = softplusf(z) - y[idx ? (int64_t)idx[r] : r];
+                r2 += res * res;
+                dz = two_n * res / (1.f + expf(-z));
+                T.DZ[r] = dz;
+            }
+            sdz[w][l] = dz;
         }
-        for (int k = 0; k < NH; ++k) {  // D2 = (W3^T D3) (1 - H2^2)
-            float a = 0.f;
-#pragma unroll
-            for (int c = 0; c < NH; ++c) a += P[OFF_W3 + c * NH + k] * d[c];
-            const float h = T.H2[s * NH + k];
-            T.D2[s * NH + k] = a * (1.f - h * h);
+        __builtin_amdgcn_wave_barrier();
+        // D3 = dz w4 (1 - H3^2)
+        for (int q = l; q < RW * NH; q += 64) {
+            const int rr = q / NH, c = q - rr * NH;
+            const int64_t r = base + w * RW + rr;
+            float d = 0.f;
+            if (r < n) {
+                const float h = T.H3[r * NH + c];
+                d = sdz[w][rr] * sw4[c] * (1.f - h * h);
+                T.D3[r * NH + c] = d;
+            }
+            sH[w][rr][c] = d;
         }
+        __builtin_amdgcn_wave_barrier();
+        // D2 from D3 through W3, then D1 from D2 through W2
 #pragma unroll
-        for (int c = 0; c < NH; ++c) d[c] = T.D2[s * NH + c];
-        for (int k = 0; k < NH; ++k) {  // D1 = (W2^T D2) (1 - H1^2)
-            float a = 0.f;
+        for (int layer = 0; layer < 2; ++layer) {
+            const float(*Wl)[NH + 1] = layer == 0 ? sW3 : sW2;
+            const float *H = layer == 0 ? T.H2 : T.H1;
+            float *D = layer == 0 ? T.D2 : T.D1;
+            f4 acc[RT][4];
 #pragma unroll
-            for (int c = 0; c < NH; ++c) a += P[OFF_W2 + c * NH + k] * d[c];
-            const float h = T.H1[s * NH + k];
-            T.D1[s * NH + k] = a * (1.f - h * h);
+            for (int ti = 0; ti < RT; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = f4{0.f, 0.f, 0.f, 0.f};
+            for (int ks = 0; ks < NH / 4; ++ks) {
+                float a[RT], b[4];
+#pragma unroll
+                for (int t = 0; t < RT; ++t) a[t] = sH[w][16 * t + li][4 * ks + lk];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) b[t] = Wl[4 * ks + lk][16 * t + li];
+#pragma unroll
+                for (int ti = 0; ti < RT; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < 4; ++tj)
+                        acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int ti = 0; ti < RT; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) sH[w][16 * ti + 4 * lk + q][16 * tj + li] = acc[ti][tj][q];
+            __builtin_amdgcn_wave_barrier();
+            for (int q = l; q < RW * NH; q += 64) {
+                const int rr = q / NH, c = q - rr * NH;
+                const int64_t r = base + w * RW + rr;
+                float d = 0.f;
+                if (r < n) {
+                    const float h = H[r * NH + c];
+                    d = sH[w][rr][c] * (1.f - h * h);
+                    D[r * NH + c] = d;
+                }
+                sH[w][rr][c] = d;
+            }
+            __builtin_amdgcn_wave_barrier();
         }
     }
-    red[threadIdx.x] = r2;
+    red[tid] = r2;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    for (int k = 128; k > 0; k >>= 1) {
+        if (tid < k) red[tid] += red[tid + k];
         __syncthreads();
     }
-    if (threadIdx.x == 0) T.part[blockIdx.x] = red[0];
+    if (tid == 0) T.part[blockIdx.x] = red[0];
 }
 
 // partial gradients: one thread per trainable parameter and chunk of samples
@@ -335,12 +397,14 @@ __global__ void k_train_loss(const float *part, int nb, int64_t n, float *out)
 void launch_gradient(const float *P, const float *X, const float *y, const int32_t *idx, int64_t n, TrainWork T,
                      float *dloss, hipStream_t st)
 {
-    const int64_t nb = train_blocks(n);
     int64_t nbf = (n + 4 * RW - 1) / (4 * RW);
     if (nbf > 4096) nbf = 4096;
     hipLaunchKernelGGL(k_mlp<true>, dim3((unsigned)nbf), dim3(256), 0, st, P, X, idx, n, 1.f, nullptr, nullptr, T);
-    hipLaunchKernelGGL(k_train_bwd, dim3((unsigned)nb), dim3(256), 0, st, P, y, idx, n, T);
-    hipLaunchKernelGGL(k_train_loss, dim3(1), dim3(64), 0, st, T.part, (int)nb, n, dloss);
+    // one loss partial per backward workgroup: at most train_blocks(n) of them
+    int64_t nbb = train_blocks(n);
+    if (nbb > 4096) nbb = 4096;
+    hipLaunchKernelGGL(k_train_bwd, dim3((unsigned)nbb), dim3(256), 0, st, P, y, idx, n, T);
+    hipLaunchKernelGGL(k_train_loss, dim3(1), dim3(64), 0, st, T.part, (int)nbb, n, dloss);
     const unsigned gq = (NTRAIN + 255) / 256;
     const int64_t nchunk = wgrad_chunks(n);
     const unsigned gy = (unsigned)(nchunk < 65535 ? nchunk : 65535);
