@@ -41,6 +41,27 @@ __device__ __forceinline__ float guard_dtau(float d, float tau, float dmax)
     return (d == d && d >= 0.f && d <= dmax * tau) ? d : 0.f;
 }
 
+// W2 and W3 into LDS by a workgroup of 256 threads: every load of a thread is
+// issued before its first LDS store, so the workgroup waits for one memory
+// round trip instead of one per loop iteration.
+__device__ __forceinline__ void stage_hidden(const float *__restrict__ P, float (*sW2)[NH + 1],
+                                             float (*sW3)[NH + 1], int tid)
+{
+    constexpr int PER = NH * NH / 256;
+    float a[PER], b[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        a[i] = P[OFF_W2 + tid + 256 * i];
+        b[i] = P[OFF_W3 + tid + 256 * i];
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int q = tid + 256 * i;
+        sW2[q / NH][q % NH] = a[i];
+        sW3[q / NH][q % NH] = b[i];
+    }
+}
+
 // Work layout (floats): Xn[n][8], H1, H2, H3, D1, D2, D3 [n][64], Z[n], DZ[n],
 // grad[NTRAIN], loss partials [nblk] and the loss, weight-gradient partials
 // [nchunk][NTRAIN].
@@ -76,26 +97,43 @@ __global__ void __launch_bounds__(256) k_mlp(const float *__restrict__ P, const 
     __shared__ float sH[4][RW][NH + 1];
     __shared__ float smean[NF], sistd[NF];
     const int tid = threadIdx.x;
-    for (int q = tid; q < NH * 8; q += 256) {
-        const int r = q / 8, c = q % 8;
-        sW1[r][c] = (c < NF) ? P[OFF_W1 + r * NF + c] : 0.f;
-    }
-    for (int q = tid; q < NH * NH; q += 256) {
-        sW2[q / NH][q % NH] = P[OFF_W2 + q];
-        sW3[q / NH][q % NH] = P[OFF_W3 + q];
-    }
-    if (tid < NH) {
-        sb1[tid] = P[OFF_B1 + tid];
-        sb2[tid] = P[OFF_B2 + tid];
-        sb3[tid] = P[OFF_B3 + tid];
-        sw4[tid] = P[OFF_W4 + tid];
-    }
-    if (tid < NF) {
-        smean[tid] = P[OFF_MEAN + tid];
-        sistd[tid] = 1.f / P[OFF_STD + tid];
+    const float b4 = P[OFF_B4], dmax = P[OFF_DMAX];
+    {
+        // all loads first (one round trip), then the LDS stores
+        float w1v[2], bv[4] = {0.f, 0.f, 0.f, 0.f}, mv = 0.f, sv = 1.f;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int q = tid + 256 * i, r = q / 8, c = q % 8;
+            w1v[i] = (c < NF) ? P[OFF_W1 + r * NF + c] : 0.f;
+        }
+        if (tid < NH) {
+            bv[0] = P[OFF_B1 + tid];
+            bv[1] = P[OFF_B2 + tid];
+            bv[2] = P[OFF_B3 + tid];
+            bv[3] = P[OFF_W4 + tid];
+        }
+        if (tid < NF) {
+            mv = P[OFF_MEAN + tid];
+            sv = P[OFF_STD + tid];
+        }
+        stage_hidden(P, sW2, sW3, tid);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int q = tid + 256 * i;
+            sW1[q / 8][q % 8] = w1v[i];
+        }
+        if (tid < NH) {
+            sb1[tid] = bv[0];
+            sb2[tid] = bv[1];
+            sb3[tid] = bv[2];
+            sw4[tid] = bv[3];
+        }
+        if (tid < NF) {
+            smean[tid] = mv;
+            sistd[tid] = 1.f / sv;
+        }
     }
     __syncthreads();
-    const float b4 = P[OFF_B4], dmax = P[OFF_DMAX];
     const int w = tid / 64, l = tid % 64;
     const int li = l & 15, lk = l >> 4;
     for (int64_t base = (int64_t)blockIdx.x * (4 * RW); base < n; base += (int64_t)gridDim.x * (4 * RW)) {
@@ -207,7 +245,12 @@ __global__ void __launch_bounds__(256) k_mlp(const float *__restrict__ P, const 
 }
 
 // ------------------------------------------------------------- training --
-int64_t train_blocks(int64_t n) { return (n + 255) / 256; }
+// backward workgroups: one tile of 4 RW rows each, at most 4096
+int64_t train_blocks(int64_t n)
+{
+    const int64_t b = (n + 4 * RW - 1) / (4 * RW);
+    return b < 4096 ? b : 4096;
+}
 
 // The weight gradient sums over the samples in chunks (at least 64 samples,
 // at most 1024 chunks), then over the chunks in order: the result does not
@@ -238,11 +281,12 @@ TrainWork carve_work(float *w, int64_t n)
 }
 
 // Back-propagation of the mean squared error of softplus(z) against y, on
-// the tiles of k_mlp: each wavefront takes RW rows; the deltas of a layer
-// are formed in its private LDS buffer, D_l = (D_{l+1} W_{l+1}) (1 - H_l^2)
-// with v_mfma_f32_16x16x4f32 (A = deltas, B = W), and stored row by row.
-// dz = (2/n) (softplus(z) - y) sigmoid(z); D3 = dz w4 (1 - H3^2). One loss
-// partial (sum of squared residuals) per workgroup.
+// the tiles of k_mlp (one tile of 4 RW rows per workgroup): the deltas of a
+// layer are formed in the wavefront's LDS buffer, D_l = (D_{l+1} W_{l+1}) (1 -
+// H_l^2) with v_mfma_f32_16x16x4f32 (A = deltas, B = W), and stored row by row.
+// dz = (2/n) (softplus(z) - y) sigmoid(z); D3 = dz w4 (1 - H3^2). Lane l holds
+// column l of the wavefront's activations, loaded before any delta is stored.
+// One loss partial (sum of squared residuals) per workgroup.
 __global__ void __launch_bounds__(256) k_train_bwd(const float *__restrict__ P, const float *__restrict__ y,
                                                    const int32_t *__restrict__ idx, int64_t n, TrainWork T)
 {
@@ -252,51 +296,62 @@ __global__ void __launch_bounds__(256) k_train_bwd(const float *__restrict__ P, 
     __shared__ float sH[4][RW][NH + 1];
     __shared__ float sdz[4][RW];
     __shared__ float red[256];
+    const float *__restrict__ H1 = T.H1;
+    const float *__restrict__ H2 = T.H2;
+    const float *__restrict__ H3 = T.H3;
+    const float *__restrict__ Z = T.Z;
+    float *__restrict__ D1 = T.D1;
+    float *__restrict__ D2 = T.D2;
+    float *__restrict__ D3 = T.D3;
+    float *__restrict__ DZ = T.DZ;
     const int tid = threadIdx.x;
-    for (int q = tid; q < NH * NH; q += 256) {
-        sW2[q / NH][q % NH] = P[OFF_W2 + q];
-        sW3[q / NH][q % NH] = P[OFF_W3 + q];
+    {
+        const float w4 = tid < NH ? P[OFF_W4 + tid] : 0.f;
+        stage_hidden(P, sW2, sW3, tid);
+        if (tid < NH) sw4[tid] = w4;
     }
-    if (tid < NH) sw4[tid] = P[OFF_W4 + tid];
     __syncthreads();
     const int w = tid / 64, l = tid % 64;
     const int li = l & 15, lk = l >> 4;
     const float two_n = 2.f / float(n);
     float r2 = 0.f;
     for (int64_t base = (int64_t)blockIdx.x * (4 * RW); base < n; base += (int64_t)gridDim.x * (4 * RW)) {
+        const int64_t r0 = base + w * RW;  // the wavefront's first row
+        float h1[RW], h2[RW], h3[RW];
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+            const bool ok = r0 + i < n;
+            h1[i] = ok ? H1[(r0 + i) * NH + l] : 0.f;
+            h2[i] = ok ? H2[(r0 + i) * NH + l] : 0.f;
+            h3[i] = ok ? H3[(r0 + i) * NH + l] : 0.f;
+        }
         // residual and dz of the wavefront's rows
         if (l < RW) {
-            const int64_t r = base + w * RW + l;
+            const int64_t r = r0 + l;
             float dz = 0.f;
             if (r < n) {
-                const float z = T.Z[r];
+                const float z = Z[r];
                 const float res = softplusf(z) - y[idx ? (int64_t)idx[r] : r];
                 r2 += res * res;
                 dz = two_n * res / (1.f + expf(-z));
-                T.DZ[r] = dz;
+                DZ[r] = dz;
             }
             sdz[w][l] = dz;
         }
         __builtin_amdgcn_wave_barrier();
         // D3 = dz w4 (1 - H3^2)
-        for (int q = l; q < RW * NH; q += 64) {
-            const int rr = q / NH, c = q - rr * NH;
-            const int64_t r = base + w * RW + rr;
-            float d = 0.f;
-            if (r < n) {
-                const float h = T.H3[r * NH + c];
-                d = sdz[w][rr] * sw4[c] * (1.f - h * h);
-                T.D3[r * NH + c] = d;
-            }
-            sH[w][rr][c] = d;
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+            const float d = sdz[w][i] * sw4[l] * (1.f - h3[i] * h3[i]);
+            if (r0 + i < n) D3[(r0 + i) * NH + l] = d;
+            sH[w][i][l] = d;
         }
         __builtin_amdgcn_wave_barrier();
         // D2 from D3 through W3, then D1 from D2 through W2
 #pragma unroll
         for (int layer = 0; layer < 2; ++layer) {
             const float(*Wl)[NH + 1] = layer == 0 ? sW3 : sW2;
-            const float *H = layer == 0 ? T.H2 : T.H1;
-            float *D = layer == 0 ? T.D2 : T.D1;
+            float *__restrict__ D = layer == 0 ? D2 : D1;
             f4 acc[RT][4];
 #pragma unroll
             for (int ti = 0; ti < RT; ++ti)
@@ -322,16 +377,12 @@ __global__ void __launch_bounds__(256) k_train_bwd(const float *__restrict__ P, 
 #pragma unroll
                     for (int q = 0; q < 4; ++q) sH[w][16 * ti + 4 * lk + q][16 * tj + li] = acc[ti][tj][q];
             __builtin_amdgcn_wave_barrier();
-            for (int q = l; q < RW * NH; q += 64) {
-                const int rr = q / NH, c = q - rr * NH;
-                const int64_t r = base + w * RW + rr;
-                float d = 0.f;
-                if (r < n) {
-                    const float h = H[r * NH + c];
-                    d = sH[w][rr][c] * (1.f - h * h);
-                    D[r * NH + c] = d;
-                }
-                sH[w][rr][c] = d;
+#pragma unroll
+            for (int i = 0; i < RW; ++i) {
+                const float h = layer == 0 ? h2[i] : h1[i];
+                const float d = sH[w][i][l] * (1.f - h * h);
+                if (r0 + i < n) D[(r0 + i) * NH + l] = d;
+                sH[w][i][l] = d;
             }
             __builtin_amdgcn_wave_barrier();
         }
@@ -345,52 +396,102 @@ __global__ void __launch_bounds__(256) k_train_bwd(const float *__restrict__ P, 
     if (tid == 0) T.part[blockIdx.x] = red[0];
 }
 
-// partial gradients: one thread per trainable parameter and chunk of samples
-// (blockIdx.y, then every gridDim.y-th chunk), summed in sample order
-__global__ void __launch_bounds__(256) k_train_wgrad(int64_t n, int64_t chunk, int64_t nchunk, TrainWork T)
+// Partial gradients of one chunk of samples per workgroup. The weight blocks
+// G_l[m][k] = sum_s D_l[s][m] A_{l-1}[s][k] of W1 (inputs padded to 8
+// columns), W2 and W3 run on v_mfma_f32_16x16x4f32 with A = D^T and B =
+// A_{l-1}, wavefront w taking the output rows 16 w .. 16 w + 15; the biases,
+// w4 and b4 are plain sums in sample order.
+__global__ void __launch_bounds__(256) k_train_wgrad(int64_t n, int64_t chunk, TrainWork T)
 {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= NTRAIN) return;
-    const int o = q + OFF_TRAIN;
-    const float *D, *Aa;
-    int m, k, K;
-    bool bias = false;
-    if (o < OFF_B1) { D = T.D1; Aa = T.Xn; K = 8; m = (o - OFF_W1) / NF; k = (o - OFF_W1) % NF; }
-    else if (o < OFF_W2) { D = T.D1; Aa = nullptr; K = 0; m = o - OFF_B1; k = 0; bias = true; }
-    else if (o < OFF_B2) { D = T.D2; Aa = T.H1; K = NH; m = (o - OFF_W2) / NH; k = (o - OFF_W2) % NH; }
-    else if (o < OFF_W3) { D = T.D2; Aa = nullptr; K = 0; m = o - OFF_B2; k = 0; bias = true; }
-    else if (o < OFF_B3) { D = T.D3; Aa = T.H2; K = NH; m = (o - OFF_W3) / NH; k = (o - OFF_W3) % NH; }
-    else if (o < OFF_W4) { D = T.D3; Aa = nullptr; K = 0; m = o - OFF_B3; k = 0; bias = true; }
-    else if (o < OFF_B4) { D = T.DZ; Aa = T.H3; K = NH; m = 0; k = o - OFF_W4; }
-    else { D = T.DZ; Aa = nullptr; K = 0; m = 0; k = 0; bias = true; }
-    const int Dstride = (D == T.DZ) ? 1 : NH;
-    for (int64_t c = blockIdx.y; c < nchunk; c += gridDim.y) {
-        const int64_t s1 = (c + 1) * chunk < n ? (c + 1) * chunk : n;
-        float g = 0.f;
-        for (int64_t s = c * chunk; s < s1; ++s) {
-            const float dv = D[s * Dstride + m];
-            g += bias ? dv : dv * Aa[s * K + k];
+    const int64_t s0 = (int64_t)blockIdx.x * chunk;
+    const int64_t s1 = s0 + chunk < n ? s0 + chunk : n;
+    const float *__restrict__ Xn = T.Xn;
+    const float *__restrict__ H1 = T.H1;
+    const float *__restrict__ H2 = T.H2;
+    const float *__restrict__ H3 = T.H3;
+    const float *__restrict__ D1 = T.D1;
+    const float *__restrict__ D2 = T.D2;
+    const float *__restrict__ D3 = T.D3;
+    const float *__restrict__ DZ = T.DZ;
+    float *__restrict__ out = T.wpart + (int64_t)blockIdx.x * NTRAIN;
+    const int tid = threadIdx.x, w = tid / 64, l = tid % 64;
+    const int li = l & 15, lk = l >> 4;
+    const int m = 16 * w + li;  // the output row this lane feeds as A
+    f4 g1 = {0.f, 0.f, 0.f, 0.f}, g2[4], g3[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) g2[t] = g3[t] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+    for (int64_t s = s0; s < s1; s += 4) {
+        const int64_t sr = s + lk;
+        const bool ok = sr < s1;
+        const float a1 = ok ? D1[sr * NH + m] : 0.f;
+        const float a2 = ok ? D2[sr * NH + m] : 0.f;
+        const float a3 = ok ? D3[sr * NH + m] : 0.f;
+        const float b1 = (ok && li < 8) ? Xn[sr * 8 + li] : 0.f;
+        float b2[4], b3[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            b2[t] = ok ? H1[sr * NH + 16 * t + li] : 0.f;
+            b3[t] = ok ? H2[sr * NH + 16 * t + li] : 0.f;
         }
-        T.wpart[c * NTRAIN + q] = g;
+        g1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, g1, 0, 0, 0);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            g2[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, b2[t], g2[t], 0, 0, 0);
+            g3[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a3, b3[t], g3[t], 0, 0, 0);
+        }
+    }
+    // output (row 16 w + 4 lk + q, column 16 t + li) of each accumulator
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int row = 16 * w + 4 * lk + q;
+        if (li < NF) out[OFF_W1 - OFF_TRAIN + row * NF + li] = g1[q];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            out[OFF_W2 - OFF_TRAIN + row * NH + 16 * t + li] = g2[t][q];
+            out[OFF_W3 - OFF_TRAIN + row * NH + 16 * t + li] = g3[t][q];
+        }
+    }
+    // b1, b2, b3 (one thread per entry), w4 (one per weight) and b4
+    {
+        const int k = tid % NH;
+        const float *__restrict__ D = tid < 64 ? D1 : tid < 128 ? D2 : D3;
+        float g = 0.f, gb = 0.f;
+        if (tid < 192) {
+#pragma unroll 16
+            for (int64_t s = s0; s < s1; ++s) g += D[s * NH + k];
+        } else {
+#pragma unroll 16
+            for (int64_t s = s0; s < s1; ++s) {
+                const float dz = DZ[s];
+                g += dz * H3[s * NH + k];
+                gb += dz;
+            }
+        }
+        const int off = tid < 64 ? OFF_B1 : tid < 128 ? OFF_B2 : tid < 192 ? OFF_B3 : OFF_W4;
+        out[off - OFF_TRAIN + k] = g;
+        if (tid == 192) out[OFF_B4 - OFF_TRAIN] = gb;
     }
 }
 
-// the gradient: the partials summed in chunk order
-__global__ void __launch_bounds__(256) k_train_wsum(int64_t nchunk, TrainWork T)
+// the gradient: the partials summed in chunk order; the thread after the
+// last parameter sums the nb loss partials of the backward pass into *loss
+__global__ void __launch_bounds__(256) k_train_wsum(int64_t nchunk, int nb, int64_t n, TrainWork T, float *loss)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q == NTRAIN) {
+        const float *__restrict__ part = T.part;
+        float s = 0.f;
+#pragma unroll 16
+        for (int b = 0; b < nb; ++b) s += part[b];
+        loss[0] = s / float(n);
+    }
     if (q >= NTRAIN) return;
+    const float *__restrict__ wp = T.wpart;
     float g = 0.f;
-    for (int64_t c = 0; c < nchunk; ++c) g += T.wpart[c * NTRAIN + q];
+#pragma unroll 16
+    for (int64_t c = 0; c < nchunk; ++c) g += wp[c * NTRAIN + q];
     T.grad[q] = g;
-}
-
-__global__ void k_train_loss(const float *part, int nb, int64_t n, float *out)
-{
-    if (threadIdx.x != 0) return;
-    float s = 0.f;
-    for (int b = 0; b < nb; ++b) s += part[b];
-    out[0] = s / float(n);
 }
 
 // forward, back-propagation, loss and gradient of n samples into T
@@ -400,16 +501,13 @@ void launch_gradient(const float *P, const float *X, const float *y, const int32
     int64_t nbf = (n + 4 * RW - 1) / (4 * RW);
     if (nbf > 4096) nbf = 4096;
     hipLaunchKernelGGL(k_mlp<true>, dim3((unsigned)nbf), dim3(256), 0, st, P, X, idx, n, 1.f, nullptr, nullptr, T);
-    // one loss partial per backward workgroup: at most train_blocks(n) of them
-    int64_t nbb = train_blocks(n);
-    if (nbb > 4096) nbb = 4096;
+    // one loss partial per backward workgroup
+    const int64_t nbb = train_blocks(n);
     hipLaunchKernelGGL(k_train_bwd, dim3((unsigned)nbb), dim3(256), 0, st, P, y, idx, n, T);
-    hipLaunchKernelGGL(k_train_loss, dim3(1), dim3(64), 0, st, T.part, (int)nbb, n, dloss);
-    const unsigned gq = (NTRAIN + 255) / 256;
-    const int64_t nchunk = wgrad_chunks(n);
-    const unsigned gy = (unsigned)(nchunk < 65535 ? nchunk : 65535);
-    hipLaunchKernelGGL(k_train_wgrad, dim3(gq, gy), dim3(256), 0, st, n, wgrad_chunk(n), nchunk, T);
-    hipLaunchKernelGGL(k_train_wsum, dim3(gq), dim3(256), 0, st, nchunk, T);
+    const int64_t nchunk = wgrad_chunks(n);  // at most 1024
+    hipLaunchKernelGGL(k_train_wgrad, dim3((unsigned)nchunk), dim3(256), 0, st, n, wgrad_chunk(n), T);
+    hipLaunchKernelGGL(k_train_wsum, dim3((NTRAIN + 1 + 255) / 256), dim3(256), 0, st, nchunk, (int)nbb, n, T,
+                       dloss);
 }
 
 // Adam (Kingma & Ba), bias-corrected, on the trainable range
