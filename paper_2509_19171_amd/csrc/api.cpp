@@ -604,7 +604,7 @@ extern "C" int sel_apply(sel_sim *s, int32_t op, const double *fin, double *fout
         if (!rc && hipMemcpyAsync(h.data(), loc, s->tsize * n, hipMemcpyDeviceToHost, s->stream) != hipSuccess)
             rc = SEL_EDEVICE;
         if (!rc) rc = sync_check(s);
-        hipFree(loc);
+        (void)hipFree(loc);  // cleanup: the result code is already decided
         if (rc) return rc;
         // [Q][E][np] (storage type) -> [E][Q][np] FP64
         for (int a = 0; a < s->Q; ++a)

@@ -848,7 +848,7 @@ static int projection_on_device(const sel_sim *f, const sel_sim *c, double **dP)
     }
     if (hipMemcpyAsync(*dP, Pm.data(), sizeof(double) * Pm.size(), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
-        hipFree(*dP);
+        (void)hipFree(*dP);
         set_error("coarse graining: upload failed");
         return SEL_EDEVICE;
     }
@@ -863,7 +863,7 @@ extern "C" int sel_coarse_grain(const sel_sim *fine, sel_sim *coarse)
     int rc = hipStreamSynchronize(fine->stream) == hipSuccess ? SEL_OK : SEL_EDEVICE;
     if (!rc) rc = sel::coarse_dispatch(fine, coarse, dP, false, nullptr);
     if (!rc && hipStreamSynchronize(coarse->stream) != hipSuccess) rc = SEL_EDEVICE;
-    hipFree(dP);
+    (void)hipFree(dP);
     return rc;
 }
 
@@ -879,7 +879,7 @@ extern "C" int sel_closure_targets(const sel_sim *fine, sel_sim *coarse, float *
     int rc = hipStreamSynchronize(fine->stream) == hipSuccess ? SEL_OK : SEL_EDEVICE;
     if (!rc) rc = sel::coarse_dispatch(fine, coarse, dP, true, d_y);
     if (!rc && hipStreamSynchronize(coarse->stream) != hipSuccess) rc = SEL_EDEVICE;
-    hipFree(dP);
+    (void)hipFree(dP);
     return rc;
 }
 

@@ -469,7 +469,8 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK), (((MODE == M_STAGE23 || 
         if constexpr (FULL && MODE == M_STAGE23) {
             static_for<0, Q>([&](auto AA) {
                 constexpr int a = decltype(AA)::value;
-                f0q[a] = (valid && inner) ? A.f0in[si.base + (int64_t)a * si.stride] : T(0);
+                // read once per stage: non-temporal, like the metric
+                f0q[a] = (valid && inner) ? __builtin_nontemporal_load(A.f0in + si.base + (int64_t)a * si.stride) : T(0);
             });
         }
     } else {
@@ -612,7 +613,8 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK), (((MODE == M_STAGE23 || 
 #pragma unroll
     for (int m = 0; m < DIM; ++m)
 #pragma unroll
-        for (int q = 0; q < DIM; ++q) Gr[m][q] = valid ? A.Gm[(e * DIM * DIM + m * DIM + q) * NP + p] : T(0);
+        for (int q = 0; q < DIM; ++q)
+            Gr[m][q] = valid ? __builtin_nontemporal_load(A.Gm + (e * DIM * DIM + m * DIM + q) * NP + p) : T(0);
     T invw = 0;
     if (MODE != M_LOCAL && valid && inner) invw = A.invw[e * NI + pc];
 
@@ -706,7 +708,11 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK), (((MODE == M_STAGE23 || 
         if constexpr (STG) {
             // results go through LDS in global order: the element's interior
             // block [Q][NI] is one contiguous run, and the boundary
-            // contributions are written slot by slot in face order
+            // contributions are written slot by slot in face order. The
+            // interior block is written non-temporally (whole lines, not read
+            // again in this stage) so that L2 keeps the contribution slots,
+            // which neighbouring elements fill line by line, and the shared
+            // operand values.
             __syncthreads();  // every plane read done
             if (inner) {
                 static_for<0, Q>([&](auto AA) {
@@ -724,7 +730,7 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK), (((MODE == M_STAGE23 || 
             if constexpr ((Q * NI) % 4 == 0) {
                 typedef T v4 __attribute__((ext_vector_type(4)));
                 for (int q = tid; q < Q * NI / 4; q += GG::BLOCK)
-                    reinterpret_cast<v4 *>(dst)[q] = reinterpret_cast<const v4 *>(lds)[q];
+                    __builtin_nontemporal_store(reinterpret_cast<const v4 *>(lds)[q], reinterpret_cast<v4 *>(dst) + q);
             } else {
                 for (int q = tid; q < Q * NI; q += GG::BLOCK) dst[q] = lds[q];
             }
@@ -803,16 +809,20 @@ __global__ void __launch_bounds__(256) k_group(GroupArgs<T> A)
     const SIdx si = sidx_group(g, Q, A.QGi);
     // every load of the group is issued before its first store (the output
     // may alias the inputs as far as the compiler knows, which would
-    // otherwise put one memory latency per velocity on the critical path)
+    // otherwise put one memory latency per velocity on the critical path);
+    // read once per stage, so non-temporally (except the stage values of the
+    // discontinuous coupling, which the interface flux of the node across
+    // each face reads again)
     T sum[Q], v0[Q], vk[Q];
     static_for<0, Q>([&](auto AA) {
         constexpr int a = decltype(AA)::value;
         const T *r = A.rtb + (int64_t)a * A.plane;
         const int64_t ix = si.base + (int64_t)a * si.stride;
-        sum[a] = r[g];
-        if (nm > 1) sum[a] += r[A.ngp + g];
-        v0[a] = A.f0[ix];
-        vk[a] = A.fk[ix];
+        sum[a] = __builtin_nontemporal_load(r + g);
+        if (nm > 1) sum[a] += __builtin_nontemporal_load(r + A.ngp + g);
+        v0[a] = __builtin_nontemporal_load(A.f0 + ix);
+        if constexpr (DGN > 0) vk[a] = A.fk[ix];
+        else vk[a] = __builtin_nontemporal_load(A.fk + ix);
     });
     for (int t = 2; t < nm; ++t) {
         const int64_t o = 2 * A.ngp + (t - 2) * A.nmp + h;
