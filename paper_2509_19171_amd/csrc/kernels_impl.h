@@ -867,10 +867,29 @@ __global__ void __launch_bounds__(256) k_group(GroupArgs<T> A)
                 }
             }
         }
-        static_for<0, Q>([&](auto AA) {
-            constexpr int a = decltype(AA)::value;
-            interface_flux<DIM, DGN, Q, a>(sum[a], vk[a], Gr, icode, gnb, A.fk, A.QGi);
-        });
+        // face by face: every velocity across the face is loaded before the
+        // first is used (the upwind test only selects), so a face costs one
+        // memory round trip; per velocity the faces add in the order of m
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) {
+            if ((icode >> (2 * m)) & 1u) {
+                const SIdx so = sidx_group(gnb[m], Q, A.QGi);
+                T vn[Q];
+                static_for<0, Q>([&](auto AA) {
+                    constexpr int a = decltype(AA)::value;
+                    vn[a] = A.fk[so.base + (int64_t)a * so.stride];
+                });
+                const T sc = (((icode >> (2 * m + 1)) & 1u) ? T(1) : T(-1)) * T(DGN * (DGN + 1)) / T(2);
+                static_for<0, Q>([&](auto AA) {
+                    constexpr int a = decltype(AA)::value;
+                    constexpr int ex = lat_e<DIM, Q>(a, 0), ey = lat_e<DIM, Q>(a, 1), ez = lat_e<DIM, Q>(a, 2);
+                    T ne = T(ex) * Gr[m][0] + T(ey) * Gr[m][1];
+                    if constexpr (DIM == 3) ne += T(ez) * Gr[m][2];
+                    ne *= sc;
+                    if (ne < T(0)) sum[a] += ne * (vk[a] - vn[a]);
+                });
+            }
+        }
     }
     static_for<0, Q>([&](auto AA) {
         constexpr int a = decltype(AA)::value;
