@@ -276,7 +276,7 @@ extern "C" int sel_workspace_bytes(const sel_mesh *m, const sel_params *p, size_
 extern "C" int sel_destroy(sel_sim *s)
 {
     if (!s) return SEL_OK;
-    if (s->owns_ws && s->ws) hipFree(s->ws);
+    if (s->owns_ws && s->ws) (void)hipFree(s->ws);  // the handle is released whatever the free returns
     delete s;
     return SEL_OK;
 }
@@ -399,7 +399,7 @@ extern "C" int sel_init(const sel_mesh *m, const sel_params *p, const double *rh
     }
 
     auto fail = [&](int rc) {
-        hipStreamSynchronize(s->stream);
+        (void)hipStreamSynchronize(s->stream);  // drain before freeing; rc already holds the error
         sel_destroy(s);
         return rc;
     };
@@ -490,8 +490,8 @@ extern "C" int sel_step_timed(sel_sim *s, int64_t nsteps, double *ms, int64_t *l
         if (!rc && hipEventElapsedTime(&t, x.second.first, x.second.second) != hipSuccess) rc = SEL_EDEVICE;
         acc[x.first] += t;
         cnt[x.first] += 1;
-        hipEventDestroy(x.second.first);
-        hipEventDestroy(x.second.second);
+        (void)hipEventDestroy(x.second.first);
+        (void)hipEventDestroy(x.second.second);
     }
     if (rc) return rc;
     for (int k = 0; k < SEL_NKIND; ++k) {

@@ -420,7 +420,6 @@ __global__ void __launch_bounds__(256) k_train_wgrad(int64_t n, int64_t chunk, T
     f4 g1 = {0.f, 0.f, 0.f, 0.f}, g2[4], g3[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) g2[t] = g3[t] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 4
     for (int64_t s = s0; s < s1; s += 4) {
         const int64_t sr = s + lk;
         const bool ok = sr < s1;
