@@ -46,9 +46,7 @@ def algorithmic_bytes(info, Q, s):
 
     Per step (the method): 8 state accesses per local node-velocity (SSPRK3:
     read f, write f1; read f, f1, write f2; read f, f2, write f) plus the
-    metric and mass weight once per stage. The metric is dim^2 values per
-    node of a curved element and dim^2 values per affine element (where it is
-    the node's tensor weight times a constant).
+    metric and mass weight (dim^2 + 1 values per node) once per stage.
     Per launch (what each kernel must move at least, every value once):
       stage1   read the operand and write the post-collision state at every
                unique node, write the density, write interior results and
@@ -67,12 +65,10 @@ def algorithmic_bytes(info, Q, s):
     G = info["unique_nodes"]
     ng = info["groups"]
     nv = E * npn * Q
-    ea = info.get("affine_elements", 0)
-    metric = ((E - ea) * npn + ea) * dim * dim
-    step = s * (8 * nv + 3 * (metric + E * npn))
+    step = s * nv * (8 + 3 * (dim * dim + 1) / Q)
     per = {
-        "stage1": s * (2 * Q * G + G + Q * E * ni + Q * E * nb + metric),
-        "stage23": s * (Q * G + 2 * Q * E * ni + Q * E * nb + metric + 2 * E * ni),
+        "stage1": s * (2 * Q * G + G + Q * E * ni + Q * E * nb + E * npn * dim * dim),
+        "stage23": s * (Q * G + 2 * Q * E * ni + Q * E * nb + E * npn * dim * dim + 2 * E * ni),
         "assembly": s * (Q * E * nb + 3 * Q * ng + 2 * ng) + 4 * (E * nb + ng),
         "filter": s * 2 * Q * G,
         # closure: read the state at every unique node and the metric, write 6 features per node id
@@ -95,7 +91,6 @@ def time_form(case, precision, steps, warmup, torch, closure=None):
 
     sim = sel.from_case(case, precision, closure=closure)
     info = sim.mesh.info()
-    info["affine_elements"] = sim.affine_elements
     sim.step(warmup)
     sim.sync()
     stream = torch.cuda.current_stream()
@@ -291,7 +286,6 @@ def main():
                                f"N={args.order}, Re=1600, Ma=0.1, quadratic filter, SSPRK3",
                    "precision": args.precision, "elements": info["E"], "order": args.order, "Q": case.Q,
                    "local_nodes": info["E"] * info["np"], "unique_nodes": info["unique_nodes"],
-                   "affine_elements": info["affine_elements"],
                    "node_velocities": nv},
         "roofline": roof,
         "step": {"algorithmic_bytes_per_step": int(step_bytes), "achieved": round(step_gbs, 1),

@@ -191,13 +191,6 @@ int sel_velocity_gradient(sel_sim *sim, double *grad);
 /* Simulated time and step count. */
 int sel_get_time(const sel_sim *sim, double *t, int64_t *nstep);
 
-/* Number of affine elements (x linear in the reference coordinates to
- * rounding, found at sel_init). For these the metric wJ dr_m/dx_k of
- * Sec. 2.2 is the node's tensor GLL weight times a constant per element,
- * which the stage kernels use instead of reading the per-node metric;
- * curved elements read it. Does not synchronise. */
-int sel_affine_elements(const sel_sim *sim, int64_t *count);
-
 /* Operator pieces on a host state f [E][Q][np] (FP64 in and out), for
  * checking the kernels one by one. Synchronises.
  *   SEL_OP_RHS:       M^-1 (R(n.j) - C_a f) after assembly (Sec. 2.2, 2.2.1), no F*

@@ -40,7 +40,7 @@ constexpr size_t kAlign = 256;
 
 struct Plan {
     size_t total = 0;
-    size_t tabD, tabF, tabW, geoD, geoW, pcode, bpos, xyz, wJ, J, Gm, Ga, gaff, wq, invw, invMb, bmap, bown, goff, gmem, ftag,
+    size_t tabD, tabF, tabW, geoD, geoW, pcode, bpos, xyz, wJ, J, Gm, invw, invMb, bmap, bown, goff, gmem, ftag,
         wallu, f[4], rtb, rhoc, Fn, io, red, flag, posmap, hidx, nbr = 0, cl_params = 0, cl_X = 0, cl_dtau = 0;
     int nred = 0;
     bool closure = false;
@@ -113,9 +113,6 @@ Plan make_plan(const sel_mesh *m, const sel_params *p)
     L.wJ = carve(c, 8 * (size_t)(E * np));
     L.J = carve(c, 8 * (size_t)(E * np));
     L.Gm = carve(c, ts * (size_t)(E * m->dim * m->dim * np));
-    L.Ga = carve(c, ts * (size_t)(E * m->dim * m->dim));
-    L.gaff = carve(c, 4 * (size_t)E);
-    L.wq = carve(c, ts * (size_t)np);
     L.invw = carve(c, ts * (size_t)(E * m->nint + 1));
     L.invMb = carve(c, ts * (size_t)(m->ngrp + 1));
     L.bmap = carve(c, 4 * (size_t)(E * m->nbe));
@@ -156,60 +153,6 @@ std::vector<T> conv(const double *src, size_t n)
     return v;
 }
 
-// Affine elements: x is linear in the reference coordinates (checked at every
-// node against the map through the element's corner nodes, to rounding), so
-// dx/dr is constant and the metric wJ dr_m/dx_k of node p is its tensor GLL
-// weight times C_mk = J dr_m/dx_k, the cofactors of dx/dr (2D: the rotated
-// tangents), the same expressions as the per-node geometry.
-int64_t affine_elements(const sel_mesh *m, const sel::Tables &t, std::vector<double> &Ga, std::vector<int32_t> &aff)
-{
-    const int dim = m->dim, n1 = m->n1, N = m->N;
-    const int64_t E = m->E, np = m->np;
-    const int str[3] = {1, n1, n1 * n1};
-    Ga.assign((size_t)(E * dim * dim), 0.0);
-    aff.assign((size_t)E, 0);
-    int64_t count = 0;
-    for (int64_t e = 0; e < E; ++e) {
-        const double *x = m->xyz.data() + e * np * dim;
-        double a[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // a[r][q] = dx_q / dr_r
-        double scale = 0.0;
-        for (int q = 0; q < dim; ++q) scale += std::fabs(x[q]);
-        for (int r = 0; r < dim; ++r)
-            for (int q = 0; q < dim; ++q) {
-                a[r][q] = 0.5 * (x[(int64_t)N * str[r] * dim + q] - x[q]);
-                scale += std::fabs(a[r][q]);
-            }
-        const double tol = 64.0 * 2.220446049250313e-16 * scale;
-        bool ok = true;
-        for (int64_t p = 0; p < np && ok; ++p) {
-            const int idx[3] = {(int)(p % n1), (int)((p / n1) % n1), (int)(p / (n1 * n1))};
-            for (int q = 0; q < dim; ++q) {
-                double pred = x[q];
-                for (int r = 0; r < dim; ++r) pred += a[r][q] * (t.xi[idx[r]] + 1.0);
-                if (!(std::fabs(pred - x[p * dim + q]) <= tol)) ok = false;
-            }
-        }
-        if (!ok) continue;
-        double *C = Ga.data() + e * dim * dim;
-        if (dim == 2) {
-            C[0] = a[1][1];
-            C[1] = -a[1][0];
-            C[2] = -a[0][1];
-            C[3] = a[0][0];
-        } else {
-            for (int r = 0; r < 3; ++r) {
-                const double *u = a[(r + 1) % 3], *v = a[(r + 2) % 3];
-                C[r * 3 + 0] = u[1] * v[2] - u[2] * v[1];
-                C[r * 3 + 1] = u[2] * v[0] - u[0] * v[2];
-                C[r * 3 + 2] = u[0] * v[1] - u[1] * v[0];
-            }
-        }
-        aff[e] = 1;
-        ++count;
-    }
-    return count;
-}
-
 template <typename T>
 int upload_tables(sel_sim *s, const sel::Tables &t, const sel_mesh *m, std::vector<std::vector<char>> &keep)
 {
@@ -235,18 +178,6 @@ int upload_tables(sel_sim *s, const sel::Tables &t, const sel_mesh *m, std::vect
     if (put(s->geoW, W.data(), 8 * W.size())) return SEL_EDEVICE;
     std::vector<T> wu = conv<T>(m->wall_u.data(), m->wall_u.size());
     if (put(s->wallu, wu.data(), sizeof(T) * wu.size())) return SEL_EDEVICE;
-    std::vector<double> Ga, wq((size_t)m->np);
-    std::vector<int32_t> aff;
-    s->naff = affine_elements(m, t, Ga, aff);
-    for (int64_t p = 0; p < m->np; ++p) {
-        double w = t.w[p % n1] * t.w[(p / n1) % n1];
-        if (m->dim == 3) w *= t.w[p / (n1 * n1)];
-        wq[p] = w;
-    }
-    std::vector<T> Gat = conv<T>(Ga.data(), Ga.size()), wqt = conv<T>(wq.data(), wq.size());
-    if (put(s->Ga, Gat.data(), sizeof(T) * Gat.size())) return SEL_EDEVICE;
-    if (put(s->gaff, aff.data(), 4 * aff.size())) return SEL_EDEVICE;
-    if (put(s->wq, wqt.data(), sizeof(T) * wqt.size())) return SEL_EDEVICE;
     return SEL_OK;
 }
 
@@ -362,9 +293,6 @@ extern "C" int sel_init(const sel_mesh *m, const sel_params *p, const double *rh
     s->wJ = reinterpret_cast<double *>(b + L.wJ);
     s->J = reinterpret_cast<double *>(b + L.J);
     s->Gm = b + L.Gm;
-    s->Ga = b + L.Ga;
-    s->gaff = reinterpret_cast<int32_t *>(b + L.gaff);
-    s->wq = b + L.wq;
     s->invw = b + L.invw;
     s->invMb = b + L.invMb;
     s->bmap = reinterpret_cast<int32_t *>(b + L.bmap);
@@ -647,16 +575,6 @@ extern "C" int sel_get_time(const sel_sim *s, double *t, int64_t *nstep)
     }
     if (t) *t = s->time;
     if (nstep) *nstep = s->nstep;
-    return SEL_OK;
-}
-
-extern "C" int sel_affine_elements(const sel_sim *s, int64_t *count)
-{
-    if (!s || !count) {
-        set_error("sel_affine_elements: null argument");
-        return SEL_EINVAL;
-    }
-    *count = s->naff;
     return SEL_OK;
 }
 

@@ -342,8 +342,6 @@ struct StageArgs {
     int64_t plane;
     T *local;        // M_LOCAL: element contributions [Q][E][NP]
     const T *Gm, *invw, *D, *F;
-    const T *Ga, *wq;       // affine elements: metric = wq[p] Ga[e] (no per-node stream)
-    const int32_t *gaff;    // [E] 1 if affine
     const int32_t *pcode, *bmap, *ftag;
     const uint8_t *bown;
     const T *wallu;  // [ntags+1][3]
@@ -612,20 +610,11 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK), (((MODE == M_STAGE23 || 
         Dk[c] = (DIM == 3) ? A.D[k * n1 + c] : T(0);
     }
     T Gr[DIM][DIM];
-    if (valid && A.gaff[e]) {
-        // affine element: the node's tensor weight times the element's constant
-        const T wp = A.wq[p];
 #pragma unroll
-        for (int m = 0; m < DIM; ++m)
+    for (int m = 0; m < DIM; ++m)
 #pragma unroll
-            for (int q = 0; q < DIM; ++q) Gr[m][q] = wp * A.Ga[e * DIM * DIM + m * DIM + q];
-    } else {
-#pragma unroll
-        for (int m = 0; m < DIM; ++m)
-#pragma unroll
-            for (int q = 0; q < DIM; ++q)
-                Gr[m][q] = valid ? __builtin_nontemporal_load(A.Gm + (e * DIM * DIM + m * DIM + q) * NP + p) : T(0);
-    }
+        for (int q = 0; q < DIM; ++q)
+            Gr[m][q] = valid ? __builtin_nontemporal_load(A.Gm + (e * DIM * DIM + m * DIM + q) * NP + p) : T(0);
     T invw = 0;
     if (MODE != M_LOCAL && valid && inner) invw = A.invw[e * NI + pc];
 

@@ -43,9 +43,6 @@ struct Impl {
     {
         StageArgs<T> A{};
         A.Gm = static_cast<const T *>(s->Gm);
-        A.Ga = static_cast<const T *>(s->Ga);
-        A.wq = static_cast<const T *>(s->wq);
-        A.gaff = s->gaff;
         A.invw = static_cast<const T *>(s->invw);
         A.D = static_cast<const T *>(s->tabD);
         A.F = static_cast<const T *>(s->tabF);

@@ -99,10 +99,6 @@ struct sel_sim {
     double *wJ = nullptr;      // [E][np]
     double *J = nullptr;       // [E][np]
     void *Gm = nullptr;        // T [E][dim*dim][np]
-    void *Ga = nullptr;        // T [E][dim*dim]: affine elements, Gm = wq[p] Ga (cofactors of dx/dr)
-    int32_t *gaff = nullptr;   // [E]: 1 if the element is affine
-    void *wq = nullptr;        // T [np]: tensor-product GLL weights
-    int64_t naff = 0;          // number of affine elements
     void *invw = nullptr;      // T [E][nint]
     void *invMb = nullptr;     // T [ngrp]
     int32_t *bmap = nullptr;   // [E][nbe]

@@ -78,7 +78,6 @@ def load():
         "sel_set_force": [P, P],
         "sel_velocity_gradient": [P, P],
         "sel_get_time": [P, P, P],
-        "sel_affine_elements": [P, P],
         "sel_apply": [P, I32, P, P],
         "sel_geometry": [P, P, P],
         "sel_destroy": [P],
@@ -347,13 +346,6 @@ class Sim:
         t = ctypes.c_double()
         n = ctypes.c_int64()
         _check(self._lib.sel_get_time(self._h, ctypes.byref(t), ctypes.byref(n)))
-        return n.value
-
-    @property
-    def affine_elements(self):
-        """Elements whose metric the stage kernels take as constant (affine)."""
-        n = ctypes.c_int64()
-        _check(self._lib.sel_affine_elements(self._h, ctypes.byref(n)))
         return n.value
 
 

@@ -1,36 +1,34 @@
 """The benchmark's byte accounting (host logic, no GPU): the method's bytes
-per node-velocity and step, s (8 + 3 (m + 1) / Q) with m the metric values
-per node (dim^2 on curved elements, dim^2 / np on affine ones), and the
-per-launch counts of the dominant kernels."""
+per node-velocity and step, s (8 + 3 (d^2 + 1) / Q) (eight state accesses,
+and the per-node metric and mass weight once per stage), and the per-launch
+counts of the kernels."""
 import bench
 
 
-def _info(E, N, dim, ea):
+def _info(E, N, dim):
     n1 = N + 1
     np_ = n1 ** dim
     ni = (N - 1) ** dim
     return {"E": E, "np": np_, "dim": dim, "boundary_nodes_per_element": np_ - ni,
-            "unique_nodes": E * ni + 1000, "groups": 1000, "affine_elements": ea}
+            "unique_nodes": E * ni + 1000, "groups": 1000}
 
 
-def test_per_step_bytes_curved_and_affine():
+def test_per_step_bytes():
     E, N, Q = 4096, 7, 27
-    for s, curved, affine in ((4, 36.44, 32.45), (8, 72.89, 64.90)):
-        nv, step, _ = bench.algorithmic_bytes(_info(E, N, 3, 0), Q, s)
-        assert abs(step / nv - curved) < 0.01
-        nv, step, _ = bench.algorithmic_bytes(_info(E, N, 3, E), Q, s)
-        # metric d^2 per element instead of per node: d^2 / np per node
-        exact = s * (8 + 3 * (1 + 9 / 512) / Q)
-        assert abs(step / nv - exact) < 1e-9 and abs(step / nv - affine) < 0.01
+    for s, per_nv in ((4, 36.44), (8, 72.89)):
+        nv, step, _ = bench.algorithmic_bytes(_info(E, N, 3), Q, s)
+        assert nv == E * 512 * Q
+        assert abs(step / nv - s * (8 + 3 * 10 / Q)) < 1e-9
+        assert abs(step / nv - per_nv) < 0.01
 
 
-def test_per_launch_metric_term():
+def test_per_launch_counts():
     E, N, Q, s = 64, 5, 19, 4
-    _, _, cur = bench.algorithmic_bytes(_info(E, N, 3, 0), Q, s)
-    _, _, aff = bench.algorithmic_bytes(_info(E, N, 3, E), Q, s)
-    np_ = (N + 1) ** 3
-    for k in ("stage1", "stage23"):
-        assert cur[k] - aff[k] == s * (E * np_ * 9 - E * 9)
-    # the assembly, filter and closure kernels do not depend on it
-    for k in ("assembly", "filter", "features", "network"):
-        assert cur[k] == aff[k]
+    info = _info(E, N, 3)
+    _, _, per = bench.algorithmic_bytes(info, Q, s)
+    np_, nb = info["np"], info["boundary_nodes_per_element"]
+    G, ng = info["unique_nodes"], info["groups"]
+    ni = np_ - nb
+    assert per["stage23"] == s * (Q * G + 2 * Q * E * ni + Q * E * nb + E * np_ * 9 + 2 * E * ni)
+    assert per["assembly"] == s * (Q * E * nb + 3 * Q * ng + 2 * ng) + 4 * (E * nb + ng)
+    assert per["filter"] == s * 2 * Q * G
