@@ -288,6 +288,9 @@ def main():
                    "local_nodes": info["E"] * info["np"], "unique_nodes": info["unique_nodes"],
                    "node_velocities": nv},
         "roofline": roof,
+        # the same steps counted over unique nodes (each shared node once)
+        "unique_node_rate": {"value": round(info["unique_nodes"] * case.Q / (head["ms_per_step"] * 1e-3) / 1e9, 3),
+                             "unit": "GNVU/s"},
         "step": {"algorithmic_bytes_per_step": int(step_bytes), "achieved": round(step_gbs, 1),
                  "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(step_gbs / PEAK_HBM_GBS, 4)},
         "kernels": {k: {"ms_total": round(v[0], 4), "launches": v[1],
