@@ -140,11 +140,20 @@ def time_training(torch, steps=100, warmup=10, batch=4096, rows=1 << 20):
             "frac": round(tflops / PEAK_FP32_MATRIX_TFLOPS, 5), "flop_per_sample": TRAIN_FLOP_PER_ROW}
 
 
-def form_summary(f, nv, info, Q, s):
+def form_summary(f, nv, Q, s):
+    """Rate, step time and the step's algorithmic HBM fraction of one form
+    (its own mesh information: the discontinuous form has more node ids); the
+    closure form adds the bytes of its feature and network kernels."""
+    info = f["info"]
     out = {"value": round(nv / (f["ms_per_step"] * 1e-3) / 1e9, 3), "ms_per_step": round(f["ms_per_step"], 5)}
     kern = f["kernels"]
+    _, step_bytes, per = algorithmic_bytes(info, Q, s)
     if kern.get("network", (0, 0))[1]:
-        _, _, per = algorithmic_bytes(info, Q, s)
+        step_bytes += per["features"] + per["network"]
+    gbs = step_bytes / (f["ms_per_step"] * 1e-3) / 1e9
+    out["step_hbm"] = {"algorithmic_bytes_per_step": int(step_bytes), "achieved": round(gbs, 1),
+                       "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4)}
+    if kern.get("network", (0, 0))[1]:
         fms, fn = kern["features"]
         mms, mn = kern["network"]
         G = info["unique_nodes"]
@@ -297,7 +306,7 @@ def main():
                         "avg_ms": round(v[0] / v[1], 5),
                         "algorithmic_GBs": round(per_kind[k] / (v[0] / v[1] * 1e-3) / 1e9, 1)}
                     for k, v in kern.items() if v[1]},
-        "forms": {p: form_summary(f, nv, info, case.Q, 4 if p.startswith("fp32") else 8) for p, f in forms.items()},
+        "forms": {p: form_summary(f, nv, case.Q, 4 if p.startswith("fp32") else 8) for p, f in forms.items()},
         "src_hash": src_hash(),
     }
     if not args.no_other_form:
