@@ -279,8 +279,9 @@ int64_t sel_mlp_work_floats(int64_t n);
  * and its gradient with respect to the trainable range, d_grad [8833].
  * Row i is row d_idx[i] of d_X [.][6] and d_y (d_idx: device int32 [n], or
  * NULL for rows 0..n-1; the caller keeps indices in range). The gradient
- * sums over rows in index order (deterministic). loss (host, may be NULL)
- * synchronises. */
+ * is summed over fixed chunks of consecutive rows (their size depends on n
+ * only), then over the chunks in order, with no atomics: the same inputs give
+ * the same result bit for bit. loss (host, may be NULL) synchronises. */
 int sel_mlp_gradient(const float *d_params, const float *d_X, const float *d_y, const int32_t *d_idx, int64_t n,
                      float *d_work, float *d_grad, double *loss, void *stream);
 
