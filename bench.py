@@ -191,8 +191,8 @@ def cpu_baseline(case, budget_s=15.0):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--precision", default="fp32dev", choices=["fp32dev", "fp64"])
     ap.add_argument("--nel", type=int, default=16)
     ap.add_argument("--order", type=int, default=7)
