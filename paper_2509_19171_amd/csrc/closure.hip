@@ -80,6 +80,10 @@ struct TrainWork {
 // compiler scheduling barriers separate the layers: the four wavefronts of a
 // workgroup run independently.
 constexpr int RW = 32;  // rows per wavefront
+// inference grid: at most 1024 workgroups (four per CU, two resident at a
+// time), each looping over its tiles, so that a workgroup stages the weights
+// for many tiles (4096 workgroups took 1.3% longer on 1.4 M rows)
+constexpr int64_t kInferMaxBlocks = 1024;
 constexpr int RT = RW / 16;
 
 // TRAIN: the forward pass of a training step on rows idx[s] of X (all rows
@@ -762,7 +766,7 @@ int launch_mlp_infer(sel_sim *s)
 {
     const int64_t n = s->Gtot;
     int64_t nb = (n + 4 * RW - 1) / (4 * RW);
-    if (nb > 4096) nb = 4096;
+    if (nb > kInferMaxBlocks) nb = kInferMaxBlocks;
     hipLaunchKernelGGL(k_mlp<false>, dim3((unsigned)nb), dim3(256), 0, s->stream, s->cl_params, s->cl_X, nullptr, n,
                        float(s->tau), nullptr, s->cl_dtau, TrainWork{});
     hipError_t err = hipGetLastError();
@@ -891,7 +895,7 @@ extern "C" int sel_mlp_forward(const float *d_params, const float *d_X, int64_t 
     }
     if (n == 0) return SEL_OK;
     int64_t nb = (n + 4 * sel::RW - 1) / (4 * sel::RW);
-    if (nb > 4096) nb = 4096;
+    if (nb > sel::kInferMaxBlocks) nb = sel::kInferMaxBlocks;
     hipLaunchKernelGGL(sel::k_mlp<false>, dim3((unsigned)nb), dim3(256), 0, static_cast<hipStream_t>(stream), d_params,
                        d_X, nullptr, n, float(tau), d_z, d_dtau, sel::TrainWork{});
     if (hipGetLastError() != hipSuccess) {
