@@ -202,8 +202,8 @@ def main():
                     help="run only a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU decomposition is described in DESIGN.md, not built)", file=sys.stderr)
+        print(f"bench.py: the step runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the element-partitioned multi-GPU step is designed, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
