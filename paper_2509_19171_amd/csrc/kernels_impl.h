@@ -888,6 +888,58 @@ __global__ void __launch_bounds__(256) k_group(GroupArgs<T> A)
     });
 }
 
+// The continuous coupling's assembly (k_group without the interface flux)
+// with the velocities of each group split between two wavefronts: waves 2k
+// and 2k + 1 of a workgroup take the lower and upper velocities of the same
+// 64 groups (the split is uniform in each wavefront). Half the values per
+// thread, so twice the groups in flight per CU; the arithmetic of every
+// velocity is that of k_group, so the results are the same bit for bit.
+template <int A0, int A1, int Q, typename T>
+__device__ __forceinline__ void group_range(const GroupArgs<T> &A, int64_t g, int nm, int64_t h, T invM, T rho,
+                                            SIdx si)
+{
+    // every load before the first store, non-temporal (as in k_group)
+    T sum[A1 - A0], v0[A1 - A0], vk[A1 - A0];
+    static_for<A0, A1>([&](auto AA) {
+        constexpr int a = decltype(AA)::value, u = a - A0;
+        const T *r = A.rtb + (int64_t)a * A.plane;
+        const int64_t ix = si.base + (int64_t)a * si.stride;
+        sum[u] = __builtin_nontemporal_load(r + g);
+        if (nm > 1) sum[u] += __builtin_nontemporal_load(r + A.ngp + g);
+        v0[u] = __builtin_nontemporal_load(A.f0 + ix);
+        vk[u] = __builtin_nontemporal_load(A.fk + ix);
+    });
+    for (int t = 2; t < nm; ++t) {
+        const int64_t o = 2 * A.ngp + (t - 2) * A.nmp + h;
+        static_for<A0, A1>([&](auto AA) {
+            constexpr int a = decltype(AA)::value, u = a - A0;
+            sum[u] += A.rtb[(int64_t)a * A.plane + o];
+        });
+    }
+    static_for<A0, A1>([&](auto AA) {
+        constexpr int a = decltype(AA)::value, u = a - A0;
+        const int64_t ix = si.base + (int64_t)a * si.stride;
+        const T L = sum[u] * invM + A.fsc[a] * rho;
+        A.out[ix] = rk_combine(A.ca, A.cb, A.cc, v0[u], vk[u], L, A.incr);
+    });
+}
+
+template <int Q, typename T>
+__global__ void __launch_bounds__(256) k_group_split(GroupArgs<T> A)
+{
+    const int w = threadIdx.x >> 6;
+    const int64_t g = (int64_t)blockIdx.x * 128 + (w >> 1) * 64 + (threadIdx.x & 63);
+    if (g >= A.ngrp) return;
+    const int nm = A.goff[g + 1] - A.goff[g];
+    const int64_t h = (nm > 2) ? (int64_t)A.hidx[g] : 0;
+    const T invM = A.invMb[g];
+    const T rho = A.rhoc[A.Gi + g];
+    const SIdx si = sidx_group(g, Q, A.QGi);
+    constexpr int HQ = (Q + 1) / 2;
+    if (w & 1) group_range<HQ, Q, Q, T>(A, g, nm, h, invM, rho, si);
+    else group_range<0, HQ, Q, T>(A, g, nm, h, invM, rho, si);
+}
+
 // ------------------------------------------------------ closure features --
 // Per element node (learned closure; the method itself has none): velocity
 // u = sum e f / rho, its element-local gradient A_ck = du_c/dx_k (D-hat along

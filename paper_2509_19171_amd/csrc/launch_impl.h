@@ -142,7 +142,9 @@ struct Impl {
         if (B.nbr) {
             hipLaunchKernelGGL((k_group<Q, T, N>), grid, block, 0, s->stream, B);
         } else {
-            hipLaunchKernelGGL((k_group<Q, T>), grid, block, 0, s->stream, B);
+            // 128 groups per workgroup, two wavefronts per group
+            dim3 grid2((unsigned)((s->ngrp + 127) / 128));
+            hipLaunchKernelGGL((k_group_split<Q, T>), grid2, block, 0, s->stream, B);
         }
         SEL_LAUNCH_CHECK();
         return toc(s, ev);
