@@ -786,52 +786,56 @@ struct GroupArgs {
     T ca, cb, cc;
     int incr;  // ca + cb = 1 (time steps): FP32 increment form
     T fsc[kMaxQ];
-    // discontinuous coupling (k_group with DGN = N): interface table, face
+    // discontinuous coupling (k_group_split with DGN = N): interface table, face
     // tags, node index of each boundary slot and the metric
     const int32_t *nbr, *ftag, *bpos;
     const T *Gm;
 };
 
-// DGN = 0: continuous coupling. DGN = N: discontinuous coupling at order N,
-// where every group is one element-boundary node (group id e * NB + b) and
-// the upwind flux of its interface faces (interface_flux, with the operand
-// fk across each face) is added to its contribution before the mass.
-template <int Q, typename T, int DGN = 0>
-__global__ void __launch_bounds__(256) k_group(GroupArgs<T> A)
+// Shared-node assembly (one group per node id on element boundaries): the
+// member contributions summed in ascending member order (rank r wrote plane r
+// for r < 2 at g, extra plane r - 2 at hidx[g]), times the assembled inverse
+// mass, plus F*, then the RK combination. DGN = 0: continuous coupling.
+// DGN = N: discontinuous coupling at order N, where every group is one
+// element-boundary node (group id e * NB + b) and the upwind flux of its
+// interface faces (with the stage value fk across each face) is added to its
+// contribution before the mass.
+// The velocities of each group are split between two wavefronts: waves 2k
+// and 2k + 1 of a workgroup take the lower and upper velocities of the same
+// 64 groups (uniform in each wavefront), so a thread holds half the values
+// and twice the groups are in flight per CU; the arithmetic of a velocity
+// does not depend on the split.
+template <int A0, int A1, int Q, typename T, int DGN>
+__device__ __forceinline__ void group_range(const GroupArgs<T> &A, int64_t g, int nm, int64_t h, T invM, T rho,
+                                            SIdx si)
 {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= A.ngrp) return;
-    const int nm = A.goff[g + 1] - A.goff[g];
-    // member rank r wrote plane r (r < 2) at g, extra plane r - 2 at hidx[g]
-    const int64_t h = (nm > 2) ? (int64_t)A.hidx[g] : 0;
-    const T invM = A.invMb[g];
-    const T rho = A.rhoc[A.Gi + g];
-    const SIdx si = sidx_group(g, Q, A.QGi);
     // every load of the group is issued before its first store (the output
     // may alias the inputs as far as the compiler knows, which would
     // otherwise put one memory latency per velocity on the critical path);
-    // read once per stage, so non-temporally (except the stage values of the
-    // discontinuous coupling, which the interface flux of the node across
-    // each face reads again)
-    T sum[Q], v0[Q], vk[Q];
-    static_for<0, Q>([&](auto AA) {
-        constexpr int a = decltype(AA)::value;
+    // read once per stage, so non-temporally
+    T sum[A1 - A0], v0[A1 - A0], vk[A1 - A0];
+    static_for<A0, A1>([&](auto AA) {
+        constexpr int a = decltype(AA)::value, u = a - A0;
         const T *r = A.rtb + (int64_t)a * A.plane;
         const int64_t ix = si.base + (int64_t)a * si.stride;
-        sum[a] = __builtin_nontemporal_load(r + g);
-        if (nm > 1) sum[a] += __builtin_nontemporal_load(r + A.ngp + g);
-        v0[a] = __builtin_nontemporal_load(A.f0 + ix);
-        if constexpr (DGN > 0) vk[a] = A.fk[ix];
-        else vk[a] = __builtin_nontemporal_load(A.fk + ix);
+        sum[u] = __builtin_nontemporal_load(r + g);
+        if (nm > 1) sum[u] += __builtin_nontemporal_load(r + A.ngp + g);
+        v0[u] = __builtin_nontemporal_load(A.f0 + ix);
+        // the discontinuous coupling's stage values are read again by the
+        // interface flux of the node across each face: cached loads there
+        if constexpr (DGN > 0) vk[u] = A.fk[ix];
+        else vk[u] = __builtin_nontemporal_load(A.fk + ix);
     });
     for (int t = 2; t < nm; ++t) {
         const int64_t o = 2 * A.ngp + (t - 2) * A.nmp + h;
-        static_for<0, Q>([&](auto AA) {
-            constexpr int a = decltype(AA)::value;
-            sum[a] += A.rtb[(int64_t)a * A.plane + o];
+        static_for<A0, A1>([&](auto AA) {
+            constexpr int a = decltype(AA)::value, u = a - A0;
+            sum[u] += A.rtb[(int64_t)a * A.plane + o];
         });
     }
     if constexpr (DGN > 0) {
+        // upwind interface flux of the discontinuous coupling on the faces
+        // of the node that are not walls (every node is a group of one)
         constexpr int DIM = (Q == 9) ? 2 : 3;
         constexpr int n1 = DGN + 1, NP = ipow_c(n1, DIM), NB = NP - ipow_c(DGN - 1, DIM);
         constexpr int nfn = (DIM == 2) ? n1 : n1 * n1;
@@ -863,58 +867,22 @@ __global__ void __launch_bounds__(256) k_group(GroupArgs<T> A)
         for (int m = 0; m < DIM; ++m) {
             if ((icode >> (2 * m)) & 1u) {
                 const SIdx so = sidx_group(gnb[m], Q, A.QGi);
-                T vn[Q];
-                static_for<0, Q>([&](auto AA) {
-                    constexpr int a = decltype(AA)::value;
-                    vn[a] = A.fk[so.base + (int64_t)a * so.stride];
+                T vn[A1 - A0];
+                static_for<A0, A1>([&](auto AA) {
+                    constexpr int a = decltype(AA)::value, u = a - A0;
+                    vn[u] = A.fk[so.base + (int64_t)a * so.stride];
                 });
                 const T sc = (((icode >> (2 * m + 1)) & 1u) ? T(1) : T(-1)) * T(DGN * (DGN + 1)) / T(2);
-                static_for<0, Q>([&](auto AA) {
-                    constexpr int a = decltype(AA)::value;
+                static_for<A0, A1>([&](auto AA) {
+                    constexpr int a = decltype(AA)::value, u = a - A0;
                     constexpr int ex = lat_e<DIM, Q>(a, 0), ey = lat_e<DIM, Q>(a, 1), ez = lat_e<DIM, Q>(a, 2);
                     T ne = T(ex) * Gr[m][0] + T(ey) * Gr[m][1];
                     if constexpr (DIM == 3) ne += T(ez) * Gr[m][2];
                     ne *= sc;
-                    if (ne < T(0)) sum[a] += ne * (vk[a] - vn[a]);
+                    if (ne < T(0)) sum[u] += ne * (vk[u] - vn[u]);
                 });
             }
         }
-    }
-    static_for<0, Q>([&](auto AA) {
-        constexpr int a = decltype(AA)::value;
-        const int64_t ix = si.base + (int64_t)a * si.stride;
-        const T L = sum[a] * invM + A.fsc[a] * rho;
-        A.out[ix] = rk_combine(A.ca, A.cb, A.cc, v0[a], vk[a], L, A.incr);
-    });
-}
-
-// The continuous coupling's assembly (k_group without the interface flux)
-// with the velocities of each group split between two wavefronts: waves 2k
-// and 2k + 1 of a workgroup take the lower and upper velocities of the same
-// 64 groups (the split is uniform in each wavefront). Half the values per
-// thread, so twice the groups in flight per CU; the arithmetic of every
-// velocity is that of k_group, so the results are the same bit for bit.
-template <int A0, int A1, int Q, typename T>
-__device__ __forceinline__ void group_range(const GroupArgs<T> &A, int64_t g, int nm, int64_t h, T invM, T rho,
-                                            SIdx si)
-{
-    // every load before the first store, non-temporal (as in k_group)
-    T sum[A1 - A0], v0[A1 - A0], vk[A1 - A0];
-    static_for<A0, A1>([&](auto AA) {
-        constexpr int a = decltype(AA)::value, u = a - A0;
-        const T *r = A.rtb + (int64_t)a * A.plane;
-        const int64_t ix = si.base + (int64_t)a * si.stride;
-        sum[u] = __builtin_nontemporal_load(r + g);
-        if (nm > 1) sum[u] += __builtin_nontemporal_load(r + A.ngp + g);
-        v0[u] = __builtin_nontemporal_load(A.f0 + ix);
-        vk[u] = __builtin_nontemporal_load(A.fk + ix);
-    });
-    for (int t = 2; t < nm; ++t) {
-        const int64_t o = 2 * A.ngp + (t - 2) * A.nmp + h;
-        static_for<A0, A1>([&](auto AA) {
-            constexpr int a = decltype(AA)::value, u = a - A0;
-            sum[u] += A.rtb[(int64_t)a * A.plane + o];
-        });
     }
     static_for<A0, A1>([&](auto AA) {
         constexpr int a = decltype(AA)::value, u = a - A0;
@@ -924,7 +892,7 @@ __device__ __forceinline__ void group_range(const GroupArgs<T> &A, int64_t g, in
     });
 }
 
-template <int Q, typename T>
+template <int Q, typename T, int DGN = 0>
 __global__ void __launch_bounds__(256) k_group_split(GroupArgs<T> A)
 {
     const int w = threadIdx.x >> 6;
@@ -936,8 +904,8 @@ __global__ void __launch_bounds__(256) k_group_split(GroupArgs<T> A)
     const T rho = A.rhoc[A.Gi + g];
     const SIdx si = sidx_group(g, Q, A.QGi);
     constexpr int HQ = (Q + 1) / 2;
-    if (w & 1) group_range<HQ, Q, Q, T>(A, g, nm, h, invM, rho, si);
-    else group_range<0, HQ, Q, T>(A, g, nm, h, invM, rho, si);
+    if (w & 1) group_range<HQ, Q, Q, T, DGN>(A, g, nm, h, invM, rho, si);
+    else group_range<0, HQ, Q, T, DGN>(A, g, nm, h, invM, rho, si);
 }
 
 // ------------------------------------------------------ closure features --

@@ -117,7 +117,7 @@ struct Impl {
         if (int rc = tic(s, kind, ev)) return rc;
         // element contributions under the discontinuous coupling carry the
         // interface flux themselves; in the stages it is added by the
-        // assembly (k_group), where every element-boundary node is a group
+        // assembly (k_group_split), where every element-boundary node is a group
         bool dg = false;
         if constexpr (MODE == M_LOCAL) {
             dg = A.nbr != nullptr;
@@ -135,15 +135,15 @@ struct Impl {
     static int launch_group(sel_sim *s, const GroupArgs<T> &B)
     {
         if (s->ngrp == 0) return SEL_OK;
-        dim3 grid((unsigned)((s->ngrp + 255) / 256)), block(256);
+        dim3 block(256);
         hipEvent_t ev = nullptr;
         if (int rc = tic(s, 2, ev)) return rc;
         // the discontinuous coupling adds its interface flux here
+        // 128 groups per workgroup, two wavefronts per group
+        dim3 grid2((unsigned)((s->ngrp + 127) / 128));
         if (B.nbr) {
-            hipLaunchKernelGGL((k_group<Q, T, N>), grid, block, 0, s->stream, B);
+            hipLaunchKernelGGL((k_group_split<Q, T, N>), grid2, block, 0, s->stream, B);
         } else {
-            // 128 groups per workgroup, two wavefronts per group
-            dim3 grid2((unsigned)((s->ngrp + 127) / 128));
             hipLaunchKernelGGL((k_group_split<Q, T>), grid2, block, 0, s->stream, B);
         }
         SEL_LAUNCH_CHECK();
