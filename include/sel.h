@@ -93,12 +93,24 @@ typedef struct sel_params {
     int64_t closure_len;
 } sel_params;
 
-/* Mesh ingest. Copies every array (the caller keeps ownership) and checks:
- * dim in {2,3}; supported N; E >= 1; gid in [0, E*np); nodes off the element
- * faces are not shared; face_tag in [0, ntags]; 0 <= ntags <= 127; wall_u
- * given when ntags > 0.
+/* Mesh ingest: the unstructured quadrilateral/hexahedral mesh of order N of
+ * Sec. 2.2 (isoparametric elements, GLL nodes, lumped mass) with the wall
+ * faces of the flux bounce-back condition (Sec. 2.2.1). Copies every array
+ * (the caller keeps ownership) and checks: dim in {2,3}; supported N; E >= 1;
+ * gid in [0, E*np); nodes off the element faces are not shared; face_tag in
+ * [0, ntags]; 0 <= ntags <= 127; wall_u given when ntags > 0; and the
+ * geometric consistency of the numbering:
+ *   - a wall face shares none of its nodes off its edges (it lies on the
+ *     domain boundary);
+ *   - the nodes of any other face off its edges are either all unshared or
+ *     all shared with exactly one other copy, in one element, displaced by
+ *     one constant vector (zero, or a periodic translation);
+ *   - every copy of a shared node coincides with its first copy up to a sum
+ *     of at most dim of those translations (periodic edges and corners);
+ *   distances below 1e-9 of the mesh extent count as zero.
  * Element geometry (Jacobian > 0) is checked by sel_init on the device.
- * Returns SEL_EINVAL, SEL_EUNSUPPORTED or SEL_ENOMEM on failure. */
+ * Returns SEL_EINVAL (with a message naming the failed check),
+ * SEL_EUNSUPPORTED or SEL_ENOMEM on failure. */
 int sel_mesh_create(int32_t dim, int32_t N, int64_t E, const double *xyz, const int64_t *gid,
                     const int32_t *face_tag, int32_t ntags, const double *wall_u, sel_mesh **out);
 
@@ -135,7 +147,15 @@ int sel_workspace_bytes(const sel_mesh *mesh, const sel_params *p, size_t *bytes
 int sel_init(const sel_mesh *mesh, const sel_params *p, const double *rho, const double *u,
              void *dev_ws, size_t ws_bytes, void *hip_stream, sel_sim **out);
 
-/* Enqueue nsteps >= 0 time steps (asynchronous). */
+/* Enqueue nsteps >= 0 whole time steps on the simulation's stream
+ * (asynchronous). One step, in the order of the scheme summary at the end of
+ * Sec. 2.2: BGK collision with F** (Sec. 2.1, Eqs. perfect1-perfect2), the
+ * streaming operator with F* and the wall flux integrated over dt by the
+ * chosen Runge-Kutta form (Sec. 2.2, 2.2.1, 2.2.2), then the modal filter
+ * (Sec. 2.2.3; applied lazily: fused into the next step's first stage, or
+ * run at the end of the call, so the state seen after the call is filtered).
+ * Errors: SEL_EINVAL (null sim or nsteps < 0), SEL_EDEVICE (launch failure);
+ * device faults and non-finite states surface at the next synchronising call. */
 int sel_step(sel_sim *sim, int64_t nsteps);
 
 /* Same as sel_step, with HIP events recorded on the stream around every

@@ -1,10 +1,13 @@
 // Mesh ingest: validation, structural node classes and the shared-node
 // groups of the continuous-Galerkin assembly.
 #include <algorithm>
+#include <array>
 #include <climits>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <numeric>
+#include <string>
 
 #include "sel_internal.h"
 
@@ -18,6 +21,149 @@ static int ipow(int b, int e)
 }
 
 static int build_interfaces(sel_mesh *m);
+
+// Geometric consistency of the node numbering (the continuous element
+// coupling of Sec. 2.2 identifies the copies of a node; the wall flux of
+// Sec. 2.2.1 acts on the domain boundary only):
+//  - a wall face is on the domain boundary: none of its face-interior nodes
+//    (off the face's edges) is shared;
+//  - the face-interior nodes of any other face are either all unshared or all
+//    shared with exactly one copy, in one element, displaced by one constant
+//    vector: zero for an interface, a translation for a periodic pair;
+//  - every copy of every shared node coincides with the node's first copy up
+//    to a sum of at most dim such translations (edges and corners of periodic
+//    boxes are displaced along several directions at once).
+// Distances below 1e-9 of the mesh extent count as zero.
+static int check_copies(const sel_mesh *m, const std::vector<int32_t> &cnt)
+{
+    const int d = m->dim, n1 = m->n1, np = m->np, N = m->N;
+    const int64_t E = m->E, nl = E * (int64_t)np;
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int k = 0; k < d; ++k) lo[k] = hi[k] = m->xyz[k];
+    for (int64_t q = 0; q < nl; ++q)
+        for (int k = 0; k < d; ++k) {
+            lo[k] = std::min(lo[k], m->xyz[q * d + k]);
+            hi[k] = std::max(hi[k], m->xyz[q * d + k]);
+        }
+    double ext = 0.0;
+    for (int k = 0; k < d; ++k) ext = std::max(ext, hi[k] - lo[k]);
+    const double tol = 1e-9 * (ext > 0.0 ? ext : 1.0);
+    auto dist = [&](const double *a, const double *b) {
+        double s = 0.0;
+        for (int k = 0; k < d; ++k) s = std::max(s, std::fabs(a[k] - b[k]));
+        return s;
+    };
+    // copies of every node id (CSR over the local nodes, ascending)
+    std::vector<int64_t> first((size_t)nl + 1, 0), ord((size_t)nl);
+    for (int64_t q = 0; q < nl; ++q) first[m->gid[q] + 1]++;
+    for (int64_t g = 0; g < nl; ++g) first[g + 1] += first[g];
+    {
+        std::vector<int64_t> pos(first.begin(), first.end() - 1);
+        for (int64_t q = 0; q < nl; ++q) ord[pos[m->gid[q]]++] = q;
+    }
+    // face-interior nodes of each face
+    std::vector<std::vector<int>> fint(2 * d);
+    for (int p = 0; p < np; ++p) {
+        const int ijk[3] = {p % n1, (p / n1) % n1, p / (n1 * n1)};
+        for (int a = 0; a < d; ++a) {
+            if (ijk[a] != 0 && ijk[a] != N) continue;
+            bool inner = true;
+            for (int b = 0; b < d; ++b)
+                if (b != a && (ijk[b] == 0 || ijk[b] == N)) inner = false;
+            if (inner) fint[2 * a + (ijk[a] == N ? 1 : 0)].push_back(p);
+        }
+    }
+    std::vector<std::array<double, 3>> tr;  // distinct non-zero face translations
+    for (int64_t e = 0; e < E; ++e)
+        for (int fc = 0; fc < 2 * d; ++fc) {
+            const bool wall = m->ftag[e * 2 * d + fc] > 0;
+            int nshared = 0;
+            int64_t e2 = -1;
+            double d0[3] = {0, 0, 0};
+            for (size_t k = 0; k < fint[fc].size(); ++k) {
+                const int64_t q = e * np + fint[fc][k];
+                const int64_t g = m->gid[q];
+                if (cnt[g] == 1) continue;
+                if (wall) {
+                    set_error("sel_mesh_create: a wall face shares a node off its edges with another face");
+                    return SEL_EINVAL;
+                }
+                if (cnt[g] != 2) {
+                    set_error("sel_mesh_create: a node inside a face has more than two copies");
+                    return SEL_EINVAL;
+                }
+                const int64_t q2 = (ord[first[g]] == q) ? ord[first[g] + 1] : ord[first[g]];
+                double dv[3] = {0, 0, 0};
+                for (int c = 0; c < d; ++c) dv[c] = m->xyz[q2 * d + c] - m->xyz[q * d + c];
+                if (nshared == 0) {
+                    e2 = q2 / np;
+                    for (int c = 0; c < 3; ++c) d0[c] = dv[c];
+                } else if (q2 / np != e2 || dist(dv, d0) > tol) {
+                    set_error("sel_mesh_create: the copies across a face are not one element's face displaced by "
+                              "one vector (inconsistent node ids or coordinates)");
+                    return SEL_EINVAL;
+                }
+                ++nshared;
+            }
+            if (nshared != 0 && nshared != (int)fint[fc].size()) {
+                set_error("sel_mesh_create: a face is only partly shared");
+                return SEL_EINVAL;
+            }
+            const double zero[3] = {0, 0, 0};
+            if (nshared && dist(d0, zero) > tol) {
+                bool seen = false;
+                for (auto &t : tr)
+                    if (dist(t.data(), d0) <= tol) seen = true;
+                if (!seen) {
+                    if (tr.size() >= 64) {
+                        set_error("sel_mesh_create: more than 64 distinct periodic translations");
+                        return SEL_EINVAL;
+                    }
+                    tr.push_back({d0[0], d0[1], d0[2]});
+                }
+            }
+        }
+    // sums of at most dim translations (each face translation appears with both signs)
+    std::vector<std::array<double, 3>> sums{{0.0, 0.0, 0.0}};
+    for (int r = 0; r < d; ++r) {
+        const size_t n0 = sums.size();
+        for (size_t i = 0; i < n0; ++i)
+            for (auto &t : tr) {
+                std::array<double, 3> s = sums[i];
+                for (int c = 0; c < 3; ++c) s[c] += t[c];
+                bool seen = false;
+                for (auto &u : sums)
+                    if (dist(u.data(), s.data()) <= tol) seen = true;
+                if (!seen) sums.push_back(s);
+                if (sums.size() > 4096) {
+                    set_error("sel_mesh_create: too many combinations of periodic translations");
+                    return SEL_EINVAL;
+                }
+            }
+    }
+    for (int64_t g = 0; g < nl; ++g) {
+        if (first[g + 1] - first[g] < 2) continue;
+        const double *x0 = m->xyz.data() + ord[first[g]] * d;
+        for (int64_t i = first[g] + 1; i < first[g + 1]; ++i) {
+            const double *x1 = m->xyz.data() + ord[i] * d;
+            if (dist(x0, x1) <= tol) continue;
+            double dv[3] = {0, 0, 0};
+            for (int c = 0; c < d; ++c) dv[c] = x1[c] - x0[c];
+            bool ok = false;
+            for (auto &s : sums)
+                if (dist(s.data(), dv) <= tol) {
+                    ok = true;
+                    break;
+                }
+            if (!ok) {
+                set_error("sel_mesh_create: copies of node id " + std::to_string(g) +
+                          " do not coincide (nor differ by the mesh's periodic translations)");
+                return SEL_EINVAL;
+            }
+        }
+    }
+    return SEL_OK;
+}
 
 static int mesh_create(int32_t dim, int32_t N, int64_t E, const double *xyz, const int64_t *gid,
                        const int32_t *face_tag, int32_t ntags, const double *wall_u, int dg, sel_mesh **out)
@@ -130,6 +276,10 @@ static int mesh_create(int32_t dim, int32_t N, int64_t E, const double *xyz, con
                     delete m;
                     return SEL_EINVAL;
                 }
+        if (int rc = check_copies(m, cnt)) {
+            delete m;
+            return rc;
+        }
 
         // shared-node groups over element-boundary nodes, members ascending,
         // groups ordered by their first member (the owner)

@@ -123,3 +123,56 @@ def test_mesh_create_dg_ingest():
     with pytest.raises(sel.SelError) as ex:
         sel.Mesh.from_inputs(opn, "dg")
     assert ex.value.code == sel.SEL_EINVAL
+
+
+def test_mesh_ingest_rejects_inconsistent_copies():
+    """Copies sharing a node id must coincide, or differ by the mesh's periodic
+    translations (Sec. 2.2: the continuous coupling identifies them)."""
+    m = I.box_mesh(3, 3, (2, 2, 2), (0, 0, 0), (1, 1, 1), (True, True, False), wall_tags={2: (1, 2)},
+                   wall_u=[[0, 0, 0], [0.1, 0, 0]])
+    sel.Mesh.from_inputs(m)
+    # a node inside the face between elements 0 and 1 moved in one copy only
+    n1 = 4
+    p = 3 + n1 * 1 + n1 * n1 * 2  # (i, j, k) = (3, 1, 2): r+ face of element 0, off its edges
+    xyz = m.xyz.copy()
+    xyz[0, p, 1] += 0.01
+    with pytest.raises(sel.SelError) as ex:
+        sel.Mesh(3, 3, xyz, m.gid, m.face_tag, m.wall_u)
+    assert ex.value.code == sel.SEL_EINVAL and "displaced" in str(ex.value)
+    # two ids swapped inside that face: the copies no longer coincide
+    gid = m.gid.copy()
+    q = 3 + n1 * 2 + n1 * n1 * 1
+    gid[0, p], gid[0, q] = m.gid[0, q], m.gid[0, p]
+    with pytest.raises(sel.SelError) as ex:
+        sel.Mesh(3, 3, m.xyz, gid, m.face_tag, m.wall_u)
+    assert ex.value.code == sel.SEL_EINVAL
+    # a corner copy moved (edges and corners are checked against the face translations)
+    xyz = m.xyz.copy()
+    xyz[3, 0, 0] += 0.01
+    with pytest.raises(sel.SelError) as ex:
+        sel.Mesh(3, 3, xyz, m.gid, m.face_tag, m.wall_u)
+    assert ex.value.code == sel.SEL_EINVAL and "coincide" in str(ex.value)
+
+
+def test_mesh_ingest_accepts_periodic_translations():
+    """Periodic copies differ by translations (here of a skewed box, so the
+    translations are not axis-aligned); edges and corners combine them. A
+    single element along a periodic direction shares nodes with itself."""
+    A = np.array([[1.0, 0.3, 0.1], [-0.2, 0.9, 0.2], [0.1, 0.05, 1.1]])
+    m = I.box_mesh(3, 3, (2, 1, 3), (0, 0, 0), (1, 1, 1), (True, True, True), warp=lambda x: x @ A.T)
+    sel.Mesh.from_inputs(m)
+    sel.Mesh.from_inputs(I.box_mesh(2, 5, (1, 1), (0, 0), (1, 1), (True, True)))
+    sel.Mesh.from_inputs(I.case_pipe(N=3, nsq=2, nrad=2, nax=2, L=2.0).mesh)
+
+
+def test_mesh_ingest_rejects_shared_wall_face():
+    """A wall face (Sec. 2.2.1) lies on the domain boundary: none of its nodes
+    off its edges may be shared with another face."""
+    m = I.box_mesh(2, 4, (2, 2), (0, 0), (1, 1), (True, False), wall_tags={1: (1, 2)},
+                   wall_u=[[0, 0], [0.1, 0]])
+    sel.Mesh.from_inputs(m)
+    ft = m.face_tag.copy()
+    ft[0, 3] = 1  # the s+ face of element 0 is the interface with element 2
+    with pytest.raises(sel.SelError) as ex:
+        sel.Mesh(2, 4, m.xyz, m.gid, ft, m.wall_u)
+    assert ex.value.code == sel.SEL_EINVAL and "wall face" in str(ex.value)
