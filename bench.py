@@ -5,13 +5,21 @@ Workload: the 3D Taylor-Green vortex, D3Q27, periodic [0, 2 pi]^3 split into
 16^3 hexahedra of order N = 7 (4096 elements, 512 nodes each, 56.6 M
 node-velocities), Re = 1600, Ma = 0.1, the paper's quadratic filter
 (gamma = 0.1, k_c = 2), SSPRK3, inputs resident in HBM. The headline form is
-FP32 deviation storage; the FP64 form is timed beside it.
+FP32 deviation storage; the FP64, learned-closure and discontinuous forms are
+timed beside it, and the other workload shapes (2D Taylor-Green, double shear
+layer, curved channel, O-grid pipe at N = 7 and its N = 5 closure variant)
+get throughput lines of their own.
 
 Prints ONE JSON line. ``value`` is node-velocity updates per second (1e9,
-local nodes E (N+1)^3 Q per step). ``roofline`` refers to the dominant kernel
-(its average duration measured here with HIP events); ``step`` gives the same
-for the whole step against the method's algorithmic bytes; ``cpu_baseline``
-times the FP64 CPU oracle on a bounded sample of the same workload.
+local nodes E (N+1)^3 Q per step). ``roofline`` prices one later SSPRK stage
+(its element kernel plus its shared-node assembly, average launch durations
+measured here with HIP events on the library's stream) with the method's
+algorithmic bytes per node-velocity for such a stage, s (3 + (d^2 + 1)/Q):
+read the stage value and the post-collision state, write the result, read the
+metric and mass weight once per node; ``step`` gives the whole step against
+s (8 + 3 (d^2 + 1)/Q). ``cpu_baseline`` times the FP64 CPU oracle, built
+with -O2 -march=native on this host, on whole-mesh steps of the same
+workload, on all host threads and on one.
 """
 from __future__ import annotations
 
@@ -28,7 +36,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "node-velocity updates/sec (GLUPS) and % HBM roofline, FP64 vs FP32 vs closure"
 PEAK_HBM_GBS = 8000.0
-COUNTERS = os.path.join(ROOT, "profiles", "k_stage23_tgv3d_n7_q27_fp32dev_counters.json")
+COUNTERS = os.path.join(ROOT, "profiles", "tgv3d_n7_q27_fp32dev_hbm_counters.json")
 
 
 def src_hash() -> str:
@@ -41,13 +49,21 @@ def src_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(info, Q, s):
-    """Algorithmic bytes per step and per launch of each kernel kind.
+def method_bytes(dim, Q, s):
+    """The method's algorithmic bytes per node-velocity (collision recomputed
+    in registers, filter fused, so no passes of their own): SSPRK3 makes 8
+    state accesses per step (stage 1 reads f and writes f1; stages 2 and 3
+    read f, the stage value and write the next), and every stage reads the
+    metric and the mass weight (dim^2 + 1 values per node, shared by the Q
+    velocities)."""
+    geo = (dim * dim + 1) / Q
+    return {"stage1": s * (2 + geo), "later_stage": s * (3 + geo), "step": s * (8 + 3 * geo)}
 
-    Per step (the method): 8 state accesses per local node-velocity (SSPRK3:
-    read f, write f1; read f, f1, write f2; read f, f2, write f) plus the
-    metric and mass weight (dim^2 + 1 values per node) once per stage.
-    Per launch (what each kernel must move at least, every value once):
+
+def algorithmic_bytes(info, Q, s):
+    """Per step: the method's bytes (method_bytes) times the node-velocities.
+    Per launch, this implementation's own count of what each kernel must move
+    at least, every value once:
       stage1   read the operand and write the post-collision state at every
                unique node, write the density, write interior results and
                the boundary-node element contributions, read the metric;
@@ -65,7 +81,7 @@ def algorithmic_bytes(info, Q, s):
     G = info["unique_nodes"]
     ng = info["groups"]
     nv = E * npn * Q
-    step = s * nv * (8 + 3 * (dim * dim + 1) / Q)
+    step = method_bytes(dim, Q, s)["step"] * nv
     per = {
         "stage1": s * (2 * Q * G + G + Q * E * ni + Q * E * nb + E * npn * dim * dim),
         "stage23": s * (Q * G + 2 * Q * E * ni + Q * E * nb + E * npn * dim * dim + 2 * E * ni),
@@ -169,23 +185,104 @@ def form_summary(f, nv, Q, s):
     return out
 
 
-def cpu_baseline(case, budget_s=15.0):
+def cpu_baseline(case, budget_s=12.0):
+    """The FP64 oracle, built here with -O2 -march=native, on whole-mesh steps
+    of the workload: on every thread OpenMP is given (the machine's CPU share),
+    then on one thread. Each leg runs about budget_s seconds at most."""
+    import shutil
+    import tempfile
+
     import oracle
 
-    o = oracle.from_case(case)
-    t0 = time.perf_counter()
-    o.step(1)
-    t1 = time.perf_counter() - t0
-    n = 1
-    extra = int(max(0, min(8, budget_s / max(t1, 1e-3) - 1)))
-    if extra:
-        t0 = time.perf_counter()
-        o.step(extra)
-        t1 += time.perf_counter() - t0
-        n += extra
-    nv = case.nv
-    return {"value": nv * n / t1 / 1e9, "unit": "GNVU/s", "cores": oracle.get_threads(), "kind": "oracle",
-            "sample": f"{n} FP64 step(s) of the same 16^3 N=7 D3Q27 workload (whole mesh, {t1:.1f} s)"}
+    tmpdir = tempfile.mkdtemp(prefix="sel_oracle_")
+    try:
+        oracle.use_library(oracle.build(native=True, path=os.path.join(tmpdir, "liboracle_native.so")))
+        nproc = os.cpu_count()
+        try:
+            import subprocess
+
+            nproc = int(subprocess.run(["nproc"], capture_output=True, text=True, check=True).stdout.strip())
+        except Exception:
+            pass
+        threads = oracle.get_threads()
+        legs = {}
+        for name, nt in (("all_threads", threads), ("single_thread", 1)):
+            oracle.set_threads(nt)
+            o = oracle.from_case(case)
+            t0 = time.perf_counter()
+            o.step(1)
+            t1 = time.perf_counter() - t0
+            n = 1
+            extra = int(max(0, min(8, budget_s / max(t1, 1e-3) - 1)))
+            if extra:
+                t0 = time.perf_counter()
+                o.step(extra)
+                t1 += time.perf_counter() - t0
+                n += extra
+            legs[name] = {"value": case.nv * n / t1 / 1e9, "threads": nt, "steps": n, "seconds": round(t1, 2)}
+            del o
+        oracle.set_threads(threads)
+    finally:
+        shutil.rmtree(tmpdir, ignore_errors=True)
+    a = legs["all_threads"]
+    return {"value": a["value"], "unit": "GNVU/s", "cores": a["threads"], "kind": "oracle",
+            "sample": f"{a['steps']} FP64 step(s) of the same 16^3 N=7 D3Q27 workload (whole mesh, "
+                      f"{a['seconds']} s, {a['threads']} OpenMP threads; oracle built with -O2 -march=native)",
+            "single_thread": {"value": legs["single_thread"]["value"], "unit": "GNVU/s",
+                              "sample": f"{legs['single_thread']['steps']} whole-mesh step(s), "
+                                        f"{legs['single_thread']['seconds']} s"},
+            "nproc": nproc}
+
+
+def time_config(name, case, precision, steps, warmup, torch, closure=None, hbm=True):
+    """Throughput line of another workload shape (not the headline)."""
+    f = time_form(case, precision, steps, warmup, torch, closure=closure)
+    info = f["info"]
+    s = 4 if precision.startswith("fp32") else 8
+    nv, step_bytes, per = algorithmic_bytes(info, case.Q, s)
+    if closure is not None:
+        step_bytes += per["features"] + per["network"]
+    out = {"workload": name, "precision": precision + ("+closure" if closure is not None else ""),
+           "elements": info["E"], "order": info["N"], "Q": case.Q, "node_velocities": nv, "steps": steps,
+           "value": round(nv / (f["ms_per_step"] * 1e-3) / 1e9, 3), "unit": "GNVU/s",
+           "ms_per_step": round(f["ms_per_step"], 5)}
+    if hbm:
+        gbs = step_bytes / (f["ms_per_step"] * 1e-3) / 1e9
+        out["step_hbm"] = {"algorithmic_bytes_per_step": int(step_bytes), "achieved": round(gbs, 1),
+                           "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4)}
+    else:
+        out["step_hbm"] = None
+        out["note"] = "working set fits in the 256 MB last-level cache: HBM fraction not meaningful"
+    return out
+
+
+def other_configs(torch, steps):
+    """The other workload shapes, each at its configured size."""
+    from paper_2509_19171_amd import inputs as I
+
+    out = []
+    k = max(20, steps // 5)
+    for prec in ("fp64", "fp32dev"):
+        out.append(time_config("2D Taylor-Green vortex, D2Q9, 8x8 quads, N=5", I.case_tgv2d(), prec, k, 10, torch,
+                               hbm=False))
+        out.append(time_config("2D double shear layer, D2Q9, 32x32 quads, N=7, exponential filter",
+                               I.case_double_shear(), prec, k, 10, torch, hbm=False))
+        out.append(time_config("2D curved Poiseuille channel, D2Q9, 16x8 quads, N=7, FBB walls",
+                               I.case_poiseuille(curved=True), prec, k, 10, torch, hbm=False))
+    print("[bench] timing the O-grid pipe", file=sys.stderr, flush=True)
+    pipe = I.case_pipe()
+    kp = max(10, steps // 10)
+    for prec in ("fp32dev", "fp64"):
+        out.append(time_config("turbulent pipe, D3Q27, O-grid of 20,480 curved hexes, N=7, FBB wall", pipe, prec,
+                               kp, 5, torch))
+    del pipe
+    torch.cuda.empty_cache()
+    coarse = I.case_pipe(N=5)
+    blob = I.closure_blob(0, mean=[0.0] * 6, std=[1.0] * 6)
+    out.append(time_config("turbulent pipe, coarse N=5 variant, plain", coarse, "fp32dev", kp, 5, torch))
+    out.append(time_config("turbulent pipe, coarse N=5 variant, learned closure", coarse, "fp32dev", kp, 5, torch,
+                           closure=blob))
+    return out
 
 
 def main():
@@ -260,23 +357,31 @@ def main():
     nv, step_bytes, per_kind = algorithmic_bytes(info, case.Q, s)
     value = nv / (head["ms_per_step"] * 1e-3) / 1e9
     kern = head["kernels"]
-    dom = max(kern, key=lambda k: kern[k][0])
-    dom_ms = kern[dom][0] / max(kern[dom][1], 1)
-    per_launch = per_kind[dom]
-    ach = per_launch / (dom_ms * 1e-3) / 1e9
+    avg = {k: v[0] / v[1] for k, v in kern.items() if v[1]}
+    # roofline: one later SSPRK stage = its element kernel + its shared-node
+    # assembly (the assembly runs once per stage with the same work), priced
+    # with the method's bytes per node-velocity of such a stage
+    stage_ms = avg["stage23"] + avg["assembly"]
+    stage_bytes = method_bytes(info["dim"], case.Q, s)["later_stage"] * nv
+    ach = stage_bytes / (stage_ms * 1e-3) / 1e9
     traffic = None
+    counters = None
     if os.path.exists(COUNTERS):
         with open(COUNTERS) as fh:
             cnt = json.load(fh)
-        if cnt.get("src_hash") == src_hash() and cnt.get("precision") == args.precision and \
-                cnt.get("kind", "stage23") == dom:
-            traffic = cnt.get("hbm_bytes_per_launch")
-    names = {"stage1": "k_stage first SSPRK stage", "stage23": "k_stage later SSPRK stages",
-             "assembly": "k_group shared-node assembly", "filter": "k_stage end-of-call filter"}
-    roof = {"bound": "hbm", "kernel": names[dom], "achieved": round(ach, 1),
-            "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4),
-            "traffic": traffic, "algorithmic_bytes_per_launch": int(per_launch),
-            "avg_launch_ms": round(dom_ms, 5)}
+        if cnt.get("src_hash") == src_hash() and cnt.get("precision") == args.precision:
+            counters = cnt.get("hbm_bytes_per_launch", {})
+            if "stage23" in counters and "assembly" in counters:
+                traffic = int(counters["stage23"] + counters["assembly"])
+    roof = {"bound": "hbm",
+            "kernel": "later SSPRK stage: k_stage element kernel (streaming, wall flux, interior update) + "
+                      "k_group_split shared-node assembly",
+            "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4),
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": int(stage_bytes),
+            "bytes_per_node_velocity": round(method_bytes(info["dim"], case.Q, s)["later_stage"], 4),
+            "avg_launch_ms": round(stage_ms, 5),
+            "avg_launch_ms_parts": {"element": round(avg["stage23"], 5), "assembly": round(avg["assembly"], 5)}}
     step_gbs = step_bytes / (head["ms_per_step"] * 1e-3) / 1e9
     result = {
         "metric": METRIC,
@@ -304,13 +409,18 @@ def main():
                  "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(step_gbs / PEAK_HBM_GBS, 4)},
         "kernels": {k: {"ms_total": round(v[0], 4), "launches": v[1],
                         "avg_ms": round(v[0] / v[1], 5),
-                        "algorithmic_GBs": round(per_kind[k] / (v[0] / v[1] * 1e-3) / 1e9, 1)}
+                        # this implementation's own per-launch count (algorithmic_bytes)
+                        "design_bytes_per_launch": int(per_kind[k]),
+                        "design_GBs": round(per_kind[k] / (v[0] / v[1] * 1e-3) / 1e9, 1),
+                        "hbm_bytes_per_launch_counters": (counters or {}).get(k)}
                     for k, v in kern.items() if v[1]},
         "forms": {p: form_summary(f, nv, case.Q, 4 if p.startswith("fp32") else 8) for p, f in forms.items()},
         "src_hash": src_hash(),
     }
     if not args.no_other_form:
         result["closure_training"] = training
+        print("[bench] timing the other workload shapes", file=sys.stderr, flush=True)
+        result["other_configs"] = other_configs(torch, args.steps)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(case)

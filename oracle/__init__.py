@@ -23,24 +23,36 @@ RK_CODES = {"ssprk3": 0, "printed4": 1}
 COUPLING_CODES = {"cg": 0, "dg": 1}
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, OpenMP over elements)."""
-    if force or not os.path.exists(_LIB_PATH):
-        tmp = _LIB_PATH + ".tmp"
-        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-D_DEFAULT_SOURCE",
-               "-Wall", "-o", tmp, _SRC, "-lm"]
+def build(force: bool = True, native: bool = False, path: str | None = None) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP over elements, no fast-math).
+    native=True adds -march=native, for timing on the machine that runs it
+    (that build is written to ``path`` and is not portable to other hosts)."""
+    out = path or _LIB_PATH
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
+        cmd = ["gcc", "-O2"] + (["-march=native"] if native else []) + \
+              ["-fopenmp", "-fPIC", "-shared", "-std=c11", "-D_DEFAULT_SOURCE", "-Wall", "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+        os.replace(tmp, out)
+    return out
 
 
-def _load():
+def use_library(path: str) -> None:
+    """Load the oracle from another build of the same source (the native
+    build used for CPU timing); later calls use it."""
+    global _lib
+    _lib = None
+    _load(path)
+
+
+def _load(path: str | None = None):
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB_PATH):
-        build(force=True)
-    lib = ctypes.CDLL(_LIB_PATH)
+    path = path or _LIB_PATH
+    if not os.path.exists(path):
+        build(force=True, path=path)
+    lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     D = ctypes.c_double
     I = ctypes.c_int

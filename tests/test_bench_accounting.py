@@ -32,3 +32,14 @@ def test_per_launch_counts():
     assert per["stage23"] == s * (Q * G + 2 * Q * E * ni + Q * E * nb + E * np_ * 9 + 2 * E * ni)
     assert per["assembly"] == s * (Q * E * nb + 3 * Q * ng + 2 * ng) + 4 * (E * nb + ng)
     assert per["filter"] == s * 2 * Q * G
+
+
+def test_stage_bytes_per_node_velocity():
+    """One later SSPRK stage (element kernel and assembly together) reads the
+    stage value and the post-collision state and writes the result (3 state
+    accesses) plus the metric and mass weight: FP32 3D Q27 13.48 B, 2D Q9
+    4 (3 + 5/9); the three stages add up to the step's figure."""
+    b = bench.method_bytes(3, 27, 4)
+    assert abs(b["later_stage"] - 4 * (3 + 10 / 27)) < 1e-12 and abs(b["later_stage"] - 13.48) < 0.005
+    assert abs(b["stage1"] + 2 * b["later_stage"] - b["step"]) < 1e-12
+    assert abs(bench.method_bytes(2, 9, 4)["later_stage"] - 4 * (3 + 5 / 9)) < 1e-12
