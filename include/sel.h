@@ -312,6 +312,21 @@ int sel_mlp_train_step(float *d_params, float *d_m, float *d_v, const float *d_X
                        const int32_t *d_idx, int64_t n, int64_t t, double lr, double b1, double b2, double eps, float *d_work, double *loss,
                        void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * Adam step as sel_mlp_train_step, computed by the same kernels and with the
+ * same result bit for bit, but its training work memory is a fixed device
+ * array inside the library (8.75 MB per GPU, held until the process ends)
+ * instead of a d_work argument. It allocates nothing. n is limited to 4096
+ * rows (one minibatch of the training recipe); larger n returns SEL_EINVAL.
+ * Every call on a GPU uses that GPU's one array: calls that overlap on one
+ * GPU (other streams or host threads) race and must be serialised by the
+ * caller. Each call writes every work value it reads, so no clearing is
+ * needed between calls. SEL_EDEVICE if the current device cannot be used. */
+int sel_mlp_train_step_noalloc(float *d_params, float *d_m, float *d_v, const float *d_X, const float *d_y,
+                               const int32_t *d_idx, int64_t n, int64_t t, double lr, double b1, double b2, double eps,
+                               double *loss, void *stream);
+
 /* Thread-local message of the last failing call ("" if none). */
 const char *sel_last_error(void);
 

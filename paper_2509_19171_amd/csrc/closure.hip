@@ -6,6 +6,7 @@
 // Parameter blob (float32): mean[6], std[6], W1[64][6], b1[64], W2[64][64],
 // b2[64], W3[64][64], b3[64], w4[64], b4[1], dtau_max[1]. The trainable
 // parameters are the contiguous range W1 .. b4.
+#include <mutex>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -250,21 +251,21 @@ __global__ void __launch_bounds__(256) k_mlp(const float *__restrict__ P, const 
 
 // ------------------------------------------------------------- training --
 // backward workgroups: one tile of 4 RW rows each, at most 4096
-int64_t train_blocks(int64_t n)
+constexpr int64_t train_blocks(int64_t n)
 {
-    const int64_t b = (n + 4 * RW - 1) / (4 * RW);
-    return b < 4096 ? b : 4096;
+    return (n + 4 * RW - 1) / (4 * RW) < 4096 ? (n + 4 * RW - 1) / (4 * RW) : 4096;
 }
 
 // The weight gradient sums over the samples in chunks (at least 64 samples,
 // at most 1024 chunks), then over the chunks in order: the result does not
 // depend on the launch, and every chunk is a short loop of its own.
-int64_t wgrad_chunk(int64_t n)
+constexpr int64_t wgrad_chunk(int64_t n) { return (n + 1023) / 1024 < 64 ? 64 : (n + 1023) / 1024; }
+constexpr int64_t wgrad_chunks(int64_t n) { return (n + wgrad_chunk(n) - 1) / wgrad_chunk(n); }
+// floats of training work memory for n rows (layout of carve_work)
+constexpr int64_t work_floats(int64_t n)
 {
-    const int64_t c = (n + 1023) / 1024;
-    return c < 64 ? 64 : c;
+    return (8 + 6 * (int64_t)NH + 2) * n + NTRAIN + train_blocks(n) + 1 + wgrad_chunks(n) * NTRAIN;
 }
-int64_t wgrad_chunks(int64_t n) { return (n + wgrad_chunk(n) - 1) / wgrad_chunk(n); }
 
 TrainWork carve_work(float *w, int64_t n)
 {
@@ -905,10 +906,34 @@ extern "C" int sel_mlp_forward(const float *d_params, const float *d_X, int64_t 
     return SEL_OK;
 }
 
-extern "C" int64_t sel_mlp_work_floats(int64_t n)
+extern "C" int64_t sel_mlp_work_floats(int64_t n) { return sel::work_floats(n); }
+
+// one Adam step with the training work memory at d_work (both entry points)
+static int train_step(const char *who, float *d_params, float *d_m, float *d_v, const float *d_X, const float *d_y,
+                      const int32_t *d_idx, int64_t n, int64_t t, double lr, double b1, double b2, double eps,
+                      float *d_work, double *loss, void *stream)
 {
-    return (8 + 6 * (int64_t)sel::NH + 2) * n + sel::NTRAIN + sel::train_blocks(n) + 1 +
-           sel::wgrad_chunks(n) * sel::NTRAIN;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    sel::TrainWork T = sel::carve_work(d_work, n);
+    float *dloss = T.part + sel::train_blocks(n);
+    sel::launch_gradient(d_params, d_X, d_y, d_idx, n, T, dloss, st);
+    const unsigned gq = (sel::NTRAIN + 255) / 256;
+    hipLaunchKernelGGL(sel::k_adam, dim3(gq), dim3(256), 0, st, d_params, d_m, d_v, T.grad, t, float(lr), float(b1),
+                       float(b2), float(eps));
+    if (hipGetLastError() != hipSuccess) {
+        set_error(std::string(who) + ": launch failed");
+        return SEL_EDEVICE;
+    }
+    if (loss) {
+        float h = 0.f;
+        if (hipMemcpyAsync(&h, dloss, sizeof(float), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            set_error(std::string(who) + ": device error");
+            return SEL_EDEVICE;
+        }
+        *loss = h;
+    }
+    return SEL_OK;
 }
 
 extern "C" int sel_mlp_train_step(float *d_params, float *d_m, float *d_v, const float *d_X, const float *d_y,
@@ -919,27 +944,65 @@ extern "C" int sel_mlp_train_step(float *d_params, float *d_m, float *d_v, const
         set_error("sel_mlp_train_step: bad argument");
         return SEL_EINVAL;
     }
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    sel::TrainWork T = sel::carve_work(d_work, n);
-    float *dloss = T.part + sel::train_blocks(n);
-    sel::launch_gradient(d_params, d_X, d_y, d_idx, n, T, dloss, st);
-    const unsigned gq = (sel::NTRAIN + 255) / 256;
-    hipLaunchKernelGGL(sel::k_adam, dim3(gq), dim3(256), 0, st, d_params, d_m, d_v, T.grad, t, float(lr), float(b1),
-                       float(b2), float(eps));
-    if (hipGetLastError() != hipSuccess) {
-        set_error("sel_mlp_train_step: launch failed");
+    return train_step("sel_mlp_train_step", d_params, d_m, d_v, d_X, d_y, d_idx, n, t, lr, b1, b2, eps, d_work, loss,
+                      stream);
+}
+
+// ------------------------------------------------ allocation-free training --
+// The training work memory of sel_mlp_train_step_noalloc: one file-scope
+// device array (each GPU the library runs on holds its own copy until the
+// process ends). Host code never passes the array's name to a kernel (on the
+// host it only stands for the symbol): the device address is looked up once
+// per device with hipGetSymbolAddress, on the first call made with that
+// device current, and kept per device. Every call writes each value of the
+// work memory it later reads (forward activations, deltas, chunk partials,
+// gradient, loss), so nothing needs clearing between calls.
+constexpr int64_t kNoAllocRows = 4096;
+constexpr int64_t kNoAllocFloats = sel::work_floats(kNoAllocRows);
+static __device__ __align__(256) float scratch[kNoAllocFloats];
+
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static float *g_scratch_ptr[kMaxDevices] = {};
+
+static int scratch_of_current_device(float **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        set_error("sel_mlp_train_step_noalloc: no usable current device");
         return SEL_EDEVICE;
     }
-    if (loss) {
-        float h = 0.f;
-        if (hipMemcpyAsync(&h, dloss, sizeof(float), hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess) {
-            set_error("sel_mlp_train_step: device error");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error(std::string("sel_mlp_train_step_noalloc: hipGetSymbolAddress failed: ") + hipGetErrorString(e));
             return SEL_EDEVICE;
         }
-        *loss = h;
+        g_scratch_ptr[dev] = static_cast<float *>(p);
     }
+    *out = g_scratch_ptr[dev];
     return SEL_OK;
+}
+
+extern "C" int sel_mlp_train_step_noalloc(float *d_params, float *d_m, float *d_v, const float *d_X,
+                                          const float *d_y, const int32_t *d_idx, int64_t n, int64_t t, double lr,
+                                          double b1, double b2, double eps, double *loss, void *stream)
+{
+    if (!d_params || !d_m || !d_v || !d_X || !d_y || n < 1 || t < 1) {
+        set_error("sel_mlp_train_step_noalloc: bad argument");
+        return SEL_EINVAL;
+    }
+    if (n > kNoAllocRows) {
+        set_error("sel_mlp_train_step_noalloc: at most 4096 rows per call (its fixed work memory); use "
+                  "sel_mlp_train_step with a work buffer for larger minibatches");
+        return SEL_EINVAL;
+    }
+    float *work = nullptr;
+    if (int rc = scratch_of_current_device(&work)) return rc;
+    return train_step("sel_mlp_train_step_noalloc", d_params, d_m, d_v, d_X, d_y, d_idx, n, t, lr, b1, b2, eps, work,
+                      loss, stream);
 }
 
 extern "C" int sel_mlp_gradient(const float *d_params, const float *d_X, const float *d_y, const int32_t *d_idx,

@@ -90,6 +90,8 @@ def load():
         "sel_mlp_gradient": [P, P, P, P, I64, P, P, P, P],
         "sel_mlp_train_step": [P, P, P, P, P, P, I64, I64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                ctypes.c_double, P, P, P],
+        "sel_mlp_train_step_noalloc": [P, P, P, P, P, P, I64, I64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, P, P],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
