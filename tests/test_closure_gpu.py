@@ -272,7 +272,9 @@ def test_targets(kind, nel, Nf, Nc, Q, prec):
     e = np.abs(y - yo).max() / max(scale, 1e-30)
     say(f"  scale {scale:.3e} err {e:.2e} nonzero {np.count_nonzero(yo[:, 0])}/{yo.shape[0]}")
     assert scale > 0
-    assert e < (1e-6 if prec == "fp64" else 2e-3)
+    # the targets are written as FP32 (0.5 ulp = 6e-8 of each value) from an
+    # FP64 computation on the FP64 state
+    assert e < (2e-7 if prec == "fp64" else 2e-3)
 
 
 @pytest.mark.parametrize("name,prec,nsteps", [("tgv2d_N5", "fp64", 12), ("tgv3d_q27_N4", "fp64", 6),

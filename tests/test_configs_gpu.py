@@ -6,13 +6,17 @@ FP64 oracle and, for the channels, the analytic start-up profiles:
   - plane Poiseuille and start-up Couette flow in the curved 16 x 8 channel of
     order 7 with flux bounce-back walls: parity after 200 and 2000 steps, and
     the velocity against the series solutions after 2000 steps.
-Tolerances as in the other parity tests (FP64 1e-12 normwise with u
-normalised by max(|u|, 0.01 c); FP32 1e-5 after 200 steps), except over 2000
-steps: the rounding-order differences of the two FP64 implementations grow
-linearly with the step count (measured on the double shear layer: 1.2e-13
-after 200 steps, 1.1e-12 after 2000, about 5.5e-16 per step), so the
-2000-step FP64 bound is 2e-12; the 2000-step FP32 errors are asserted below
-1e-4 and printed."""
+Tolerances as in the other parity tests: FP64 1e-12 normwise, with u
+normalised by max(|u|, 0.01 c) (u is formed from differences of O(1)
+populations, whose FP64 rounding-order differences stay absolute when a flow
+starts from rest); FP32 deviation storage 1e-5 normwise on rho and u after
+200 steps, with no floor on u (the deviations carry the small velocities of
+a start-up flow, so the relative error stays small: measured 1.5e-6 on the
+Poiseuille start-up with max|u| = 3.4e-5). Over 2000 steps the rounding-order
+differences of the two FP64 implementations grow linearly with the step
+count (double shear layer: 1.2e-13 after 200 steps, 1.1e-12 after 2000,
+about 5.5e-16 per step), so the 2000-step FP64 bound is 2e-12; the 2000-step
+FP32 bound is 3e-5 (measured at most 1.2e-5, double shear layer)."""
 import functools
 import sys
 
@@ -33,6 +37,7 @@ def say(msg):
 
 
 def uerr(u, uref):
+    """FP64 velocity error normalised by max(max|u_ref|, 0.01 c), c = 1."""
     return float(np.abs(u - uref).max() / max(np.abs(uref).max(), 0.01))
 
 
@@ -76,14 +81,15 @@ def test_config_parity(name, prec):
     c, (r200, u200), (r2k, u2k), _ = _oracle_run(name)
     say(f"{name} {prec}")
     (gr200, gu200), (gr2k, gu2k) = _gpu_run(c, prec)
-    e = [nerr(gr200, r200), uerr(gu200, u200), nerr(gr2k, r2k), uerr(gu2k, u2k)]
+    ue = uerr if prec == "fp64" else nerr
+    e = [nerr(gr200, r200), ue(gu200, u200), nerr(gr2k, r2k), ue(gu2k, u2k)]
     say(f"  200 steps: rho {e[0]:.2e} u {e[1]:.2e}; 2000 steps: rho {e[2]:.2e} u {e[3]:.2e}")
     if prec == "fp64":
         assert e[0] < 1e-12 and e[1] < 1e-12
         assert e[2] < 2e-12 and e[3] < 2e-12
     else:
         assert e[0] < 1e-5 and e[1] < 1e-5
-        assert e[2] < 1e-4 and e[3] < 1e-4
+        assert e[2] < 3e-5 and e[3] < 3e-5
 
 
 @pytest.mark.parametrize("name", ["poiseuille", "couette"])

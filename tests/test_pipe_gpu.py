@@ -2,7 +2,8 @@
 body force along the axis, exponential filter), FP64 and FP32 deviation
 storage, at reduced size over many steps and at full size (20,480 hexes,
 N = 7) over two steps; and the learned closure on the coarse (N = 5) pipe.
-Tolerances as in the other parity tests."""
+Tolerances as in the other parity tests: FP64 1e-12 (u normalised by
+max(|u|, 0.01 c)), FP32 deviation storage normwise with no floor on u."""
 import sys
 
 import numpy as np
@@ -79,7 +80,7 @@ def test_pipe_full_size():
         g = sel.from_case(c, prec)
         g.step(2)
         rho, u = g.moments()
-        er, eu = nerr(rho, orho), uerr(u, ou)
+        er, eu = nerr(rho, orho), (uerr(u, ou) if prec == "fp64" else nerr(u, ou))
         say(f"  {prec}: rho {er:.2e} u {eu:.2e}")
         assert er < tol and eu < tol, prec
         if prec == "fp64":
@@ -110,7 +111,7 @@ def test_pipe_coarse_closure_run():
         g = sel.from_case(c, prec, closure=blob)
         g.step(8)
         rho, u = g.moments()
-        er, eu = nerr(rho, orho), uerr(u, ou)
+        er, eu = nerr(rho, orho), (uerr(u, ou) if prec == "fp64" else nerr(u, ou))
         say(f"  rho {er:.2e} u {eu:.2e}")
         assert er < tol and eu < tol
 
@@ -140,6 +141,6 @@ def test_pipe_forced_law_of_wall(prec, steps, tol):
     rho, u = g.moments()
     orho, ou = o.moments()
     er = np.abs(rho - orho).max() / np.abs(orho).max()
-    eu = np.abs(u - ou).max() / max(np.abs(ou).max(), 0.01)
+    eu = np.abs(u - ou).max() / (max(np.abs(ou).max(), 0.01) if prec == "fp64" else np.abs(ou).max())
     print(f"[gpu]   pipe forced {prec}: rho {er:.2e} u {eu:.2e}", flush=True)
     assert er < tol and eu < tol
