@@ -169,24 +169,35 @@ __device__ __forceinline__ void collide_node(T (&v)[Q], T rho0, T omega, T dt, c
         //   n' = n - t (S0 + e.S1 / cs2), f* = f-bar-eq + dt F** + (1 - omega) n + omega (n - n').
         T base[Q];
         T S0 = 0, S1x = 0, S1y = 0, S1z = 0;
-        static_for<0, Q>([&](auto A) {
-            constexpr int a = decltype(A)::value;
-            constexpr int ex = lat_e<DIM, Q>(a, 0), ey = lat_e<DIM, Q>(a, 1), ez = lat_e<DIM, Q>(a, 2);
-            const T t = T(lat_t<DIM, Q>(a));
-            const T eu = T(ex) * u0 + T(ey) * u1 + T(ez) * u2;
-            const T eF = T(ex) * F0 + T(ey) * F1 + T(ez) * F2;
-            const T poly = c1 * eu + c2 * eu * eu - c3 * uu;
-            const T feq = DEV ? t * (m0 + rho * poly) : t * rho * (T(1) + poly);
-            const T fss = t * (T(9) * eu * eF - T(3) * uF);
-            const T fbeq = feq - half_dt * fss;
-            const T n = v[a] - fbeq;
-            base[a] = fbeq + dt * fss;
-            v[a] = n;
-            S0 += n;
-            if constexpr (ex != 0) S1x += T(ex) * n;
-            if constexpr (ey != 0) S1y += T(ey) * n;
-            if constexpr (ez != 0) S1z += T(ez) * n;
-        });
+        // without a body force F** vanishes: the same values without its terms
+        const bool forced = (g[0] != T(0)) | (g[1] != T(0)) | (g[2] != T(0));
+        auto pass1 = [&](auto FORCED) {
+            static_for<0, Q>([&](auto A) {
+                constexpr int a = decltype(A)::value;
+                constexpr int ex = lat_e<DIM, Q>(a, 0), ey = lat_e<DIM, Q>(a, 1), ez = lat_e<DIM, Q>(a, 2);
+                const T t = T(lat_t<DIM, Q>(a));
+                const T eu = T(ex) * u0 + T(ey) * u1 + T(ez) * u2;
+                const T poly = c1 * eu + c2 * eu * eu - c3 * uu;
+                const T feq = DEV ? t * (m0 + rho * poly) : t * rho * (T(1) + poly);
+                T fbeq = feq;
+                if constexpr (decltype(FORCED)::value) {
+                    const T eF = T(ex) * F0 + T(ey) * F1 + T(ez) * F2;
+                    const T fss = t * (T(9) * eu * eF - T(3) * uF);
+                    fbeq = feq - half_dt * fss;
+                    base[a] = fbeq + dt * fss;
+                } else {
+                    base[a] = fbeq;
+                }
+                const T n = v[a] - fbeq;
+                v[a] = n;
+                S0 += n;
+                if constexpr (ex != 0) S1x += T(ex) * n;
+                if constexpr (ey != 0) S1y += T(ey) * n;
+                if constexpr (ez != 0) S1z += T(ez) * n;
+            });
+        };
+        if (forced) pass1(std::true_type{});
+        else pass1(std::false_type{});
         const T keep = T(1) - omega;
         static_for<0, Q>([&](auto A) {
             constexpr int a = decltype(A)::value;
@@ -343,6 +354,7 @@ struct StageArgs {
     T *local;        // M_LOCAL: element contributions [Q][E][NP]
     const T *Gm, *invw, *D, *F;
     const int32_t *pcode, *bmap, *ftag;
+    const int32_t *bpos;  // [NB] node index of each boundary slot
     const uint8_t *bown;
     const T *wallu;  // [ntags+1][3]
     int64_t E, nblk, Gi, QGi;
@@ -492,14 +504,19 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK), (((MODE == M_STAGE23 || 
                 const int row = (m == 0) ? rowr : (m == 1) ? rows : rowt;
                 constexpr int st = (m == 0) ? 1 : (m == 1) ? n1 : n1 * n1;
                 const int ir = (m == 0) ? i : (m == 1) ? j : k;
-                static_for<0, Q>([&](auto AA) {
-                    constexpr int a = decltype(AA)::value;
-                    const T x = fq[a];
-                    T t = 0;
+                // rows 0 and N of F are unit vectors: nodes at the ends of
+                // the line keep their value (exactly); along t in 3D at N = 7
+                // these are whole wavefronts (k is uniform)
+                if (!(m == DIM - 1 && (ir == 0 || ir == N))) {
+                    static_for<0, Q>([&](auto AA) {
+                        constexpr int a = decltype(AA)::value;
+                        const T x = fq[a];
+                        T t = 0;
 #pragma unroll
-                    for (int q = 0; q < n1; ++q) t += sF[ir * n1 + q] * (pl[a][row + st * q] - x);
-                    fq[a] = t + x;
-                });
+                        for (int q = 0; q < n1; ++q) t += sF[ir * n1 + q] * (pl[a][row + st * q] - x);
+                        fq[a] = t + x;
+                    });
+                }
                 if constexpr (m + 1 < DIM) {
                     __syncthreads();  // every read of this pass done
                     static_for<0, Q>([&](auto AA) {
@@ -818,8 +835,14 @@ __device__ __forceinline__ void group_range(const GroupArgs<T> &A, int64_t g, in
         constexpr int a = decltype(AA)::value, u = a - A0;
         const T *r = A.rtb + (int64_t)a * A.plane;
         const int64_t ix = si.base + (int64_t)a * si.stride;
-        sum[u] = __builtin_nontemporal_load(r + g);
-        if (nm > 1) sum[u] += __builtin_nontemporal_load(r + A.ngp + g);
+        // the rest velocity neither streams nor meets a wall flux: its
+        // contributions are zero and are not stored by the element kernels
+        if constexpr (a == 0) {
+            sum[u] = T(0);
+        } else {
+            sum[u] = __builtin_nontemporal_load(r + g);
+            if (nm > 1) sum[u] += __builtin_nontemporal_load(r + A.ngp + g);
+        }
         v0[u] = __builtin_nontemporal_load(A.f0 + ix);
         // the discontinuous coupling's stage values are read again by the
         // interface flux of the node across each face: cached loads there
@@ -830,7 +853,7 @@ __device__ __forceinline__ void group_range(const GroupArgs<T> &A, int64_t g, in
         const int64_t o = 2 * A.ngp + (t - 2) * A.nmp + h;
         static_for<A0, A1>([&](auto AA) {
             constexpr int a = decltype(AA)::value, u = a - A0;
-            sum[u] += A.rtb[(int64_t)a * A.plane + o];
+            if constexpr (a != 0) sum[u] += A.rtb[(int64_t)a * A.plane + o];
         });
     }
     if constexpr (DGN > 0) {

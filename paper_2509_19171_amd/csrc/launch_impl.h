@@ -2,6 +2,7 @@
 #pragma once
 
 #include "kernels_impl.h"
+#include "kernels_mfma.h"
 #include "ops.h"
 
 namespace sel {
@@ -19,6 +20,8 @@ template <int DIM, int N, int Q, typename T, bool DEV>
 struct Impl {
     using GG = Geo<DIM, N>;
     static constexpr int NP = GG::NP, NI = GG::NI, NB = GG::NB, EPB = GG::EPB;
+    // later-stage element kernel with matrix-core contractions (kernels_mfma.h)
+    static constexpr bool kMfma = std::is_same<T, float>::value && DEV && DIM == 3 && N == 7;
 
     static T *st(sel_sim *s, int i) { return static_cast<T *>(s->f[i]); }
     static int64_t nblk(sel_sim *s) { return (s->E + EPB - 1) / EPB; }
@@ -48,6 +51,7 @@ struct Impl {
         A.F = static_cast<const T *>(s->tabF);
         A.pcode = s->pcode;
         A.bmap = s->bmap;
+        A.bpos = s->bpos;
         A.ftag = s->ftag;
         A.bown = s->bown;
         A.wallu = static_cast<const T *>(s->wallu);
@@ -126,7 +130,12 @@ struct Impl {
             }
         }
         if (!dg) {
-            hipLaunchKernelGGL((k_stage<DIM, N, Q, T, DEV, MODE>), grid, block, 0, s->stream, A);
+            // FP32 3D order 7, later stages: vector loads and matrix-core contractions
+            if constexpr (kMfma && MODE == M_STAGE23) {
+                hipLaunchKernelGGL((k_stage23_mf<Q>), grid, block, 0, s->stream, A);
+            } else {
+                hipLaunchKernelGGL((k_stage<DIM, N, Q, T, DEV, MODE>), grid, block, 0, s->stream, A);
+            }
         }
         SEL_LAUNCH_CHECK();
         return toc(s, ev);
