@@ -176,3 +176,16 @@ def test_mesh_ingest_rejects_shared_wall_face():
     with pytest.raises(sel.SelError) as ex:
         sel.Mesh(2, 4, m.xyz, m.gid, ft, m.wall_u)
     assert ex.value.code == sel.SEL_EINVAL and "wall face" in str(ex.value)
+
+
+def test_order_beyond_one_thread_per_node_is_unsupported():
+    """3D orders are built up to N = 8 (one thread per node, at most 1024
+    nodes per workgroup); N = 12 (2197 nodes, one of the paper's Taylor-Green
+    orders) is refused with SEL_EUNSUPPORTED before any device call."""
+    c = I.case_tgv3d(nel=1, N=12, Q=19, steps=0)
+    sm = sel.Mesh.from_inputs(c.mesh)
+    with pytest.raises(sel.SelError) as ex:
+        sm.workspace_bytes(sel.params_from_case(c, "fp32dev"))
+    assert ex.value.code == sel.SEL_EUNSUPPORTED
+    c8 = I.case_tgv3d(nel=1, N=8, Q=19, steps=0)
+    assert sel.Mesh.from_inputs(c8.mesh).workspace_bytes(sel.params_from_case(c8, "fp32dev")) > 0
