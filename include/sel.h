@@ -208,6 +208,23 @@ int sel_set_force(sel_sim *sim, const double *F);
  * rate of Sec. 3.4. Synchronises. */
 int sel_velocity_gradient(sel_sim *sim, double *grad);
 
+/* Radial profile of the velocity along an axis (the averaged streamwise
+ * profile u_z(r) of the pipe case, Sec. 3.5): with the unit axis n through
+ * origin (both [dim], FP64 host; axis need not be normalised) and the radial
+ * distance r of an element node from that line, the element nodes with
+ * r < rmax fall into nbins equal bins of [0, rmax). out [2 nbins] (FP64 host)
+ * receives per bin sum wJ (u . n) in out[b] and sum wJ in out[nbins + b]
+ * (lumped-mass integrals over the bin's nodes, u = sum e f / rho of
+ * Eq. momentum), so out[b] / out[nbins + b] is the bin's space-averaged axial
+ * velocity (time averages are sums of calls). In 2D the line is the line
+ * through origin along axis (a channel profile). Deterministic: each bin is
+ * summed in ascending node order. The first call for a binning allocates its
+ * node lists on the device (kept until the binning changes or sel_destroy).
+ * Errors: SEL_EINVAL (bad argument, 1 <= nbins <= 4096, rmax > 0),
+ * SEL_ENOMEM, SEL_EDEVICE. Synchronises. */
+int sel_radial_profile(sel_sim *sim, const double *origin, const double *axis, double rmax, int32_t nbins,
+                       double *out);
+
 /* Simulated time and step count. */
 int sel_get_time(const sel_sim *sim, double *t, int64_t *nstep);
 

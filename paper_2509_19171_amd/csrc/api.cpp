@@ -204,9 +204,52 @@ extern "C" int sel_workspace_bytes(const sel_mesh *m, const sel_params *p, size_
     return SEL_OK;
 }
 
+// sums of the two per-node terms over the element nodes of each bin, in
+// the order of the bin's node list (one workgroup per bin, fixed reduction
+// tree: the result does not depend on the launch)
+static __global__ void __launch_bounds__(256) k_bin_sums(const double *terms, int64_t nl, const int32_t *nodes,
+                                                  const int32_t *off, int nbins, double *out)
+{
+    __shared__ double sh[2][256];
+    const int b = blockIdx.x;
+    double a0 = 0.0, a1 = 0.0;
+    for (int64_t k = off[b] + threadIdx.x; k < off[b + 1]; k += 256) {
+        const int64_t q = nodes[k];
+        a0 += terms[q];
+        a1 += terms[nl + q];
+    }
+    sh[0][threadIdx.x] = a0;
+    sh[1][threadIdx.x] = a1;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + st];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[b] = sh[0][0];
+        out[nbins + b] = sh[1][0];
+    }
+}
+
+static void free_profile(sel_sim *s)
+{
+    // cleanup: a failing free cannot be acted on
+    if (s->prof_nodes) (void)hipFree(s->prof_nodes);
+    if (s->prof_off) (void)hipFree(s->prof_off);
+    if (s->prof_out) (void)hipFree(s->prof_out);
+    s->prof_nodes = nullptr;
+    s->prof_off = nullptr;
+    s->prof_out = nullptr;
+    s->prof_nbins = 0;
+}
+
 extern "C" int sel_destroy(sel_sim *s)
 {
     if (!s) return SEL_OK;
+    free_profile(s);
     if (s->owns_ws && s->ws) (void)hipFree(s->ws);  // the handle is released whatever the free returns
     delete s;
     return SEL_OK;
@@ -564,6 +607,85 @@ extern "C" int sel_velocity_gradient(sel_sim *s, double *grad)
         for (int64_t l = 0; l < nl; ++l)
             for (int q = 0; q < d; ++q) grad[(l * d + c) * d + q] = row[l * d + q];
     }
+    return sync_check(s);
+}
+
+extern "C" int sel_radial_profile(sel_sim *s, const double *origin, const double *axis, double rmax, int32_t nbins,
+                                  double *out)
+{
+    if (!s || !origin || !axis || !out) {
+        set_error("sel_radial_profile: null argument");
+        return SEL_EINVAL;
+    }
+    if (nbins < 1 || nbins > 4096 || !(rmax > 0.0) || !std::isfinite(rmax)) {
+        set_error("sel_radial_profile: need 1 <= nbins <= 4096 and rmax > 0");
+        return SEL_EINVAL;
+    }
+    const int d = s->dim;
+    double n[3] = {0, 0, 0}, o[3] = {0, 0, 0}, nn = 0.0;
+    for (int k = 0; k < d; ++k) {
+        n[k] = axis[k];
+        o[k] = origin[k];
+        nn += n[k] * n[k];
+    }
+    if (!(nn > 0.0) || !std::isfinite(nn)) {
+        set_error("sel_radial_profile: axis must be a non-zero finite vector");
+        return SEL_EINVAL;
+    }
+    for (int k = 0; k < d; ++k) n[k] /= std::sqrt(nn);
+    const int64_t nl = s->E * (int64_t)s->np;
+    const double key[7] = {o[0], o[1], o[2], n[0], n[1], n[2], rmax};
+    bool same = s->prof_nbins == nbins;
+    for (int k = 0; k < 7; ++k) same = same && key[k] == s->prof_key[k];
+    if (!same) {
+        // node lists per bin from the node coordinates (ascending node order)
+        free_profile(s);
+        std::vector<double> x((size_t)nl * d);
+        HIP_OK(hipMemcpyAsync(x.data(), s->xyz, 8 * x.size(), hipMemcpyDeviceToHost, s->stream));
+        if (int rc = sync_check(s)) return rc;
+        std::vector<int32_t> bin((size_t)nl), off((size_t)nbins + 1, 0);
+        for (int64_t q = 0; q < nl; ++q) {
+            double v[3] = {0, 0, 0}, vn = 0.0;
+            for (int k = 0; k < d; ++k) {
+                v[k] = x[q * d + k] - o[k];
+                vn += v[k] * n[k];
+            }
+            double r2 = 0.0;
+            for (int k = 0; k < d; ++k) r2 += (v[k] - vn * n[k]) * (v[k] - vn * n[k]);
+            const double rb = std::sqrt(r2) / rmax * nbins;
+            bin[q] = (rb < nbins) ? (int32_t)rb : -1;
+            if (bin[q] >= 0) off[bin[q] + 1]++;
+        }
+        for (int b = 0; b < nbins; ++b) off[b + 1] += off[b];
+        std::vector<int32_t> nodes((size_t)off[nbins] + 1), pos(off.begin(), off.end() - 1);
+        for (int64_t q = 0; q < nl; ++q)
+            if (bin[q] >= 0) nodes[pos[bin[q]]++] = (int32_t)q;
+        if (hipMalloc(&s->prof_nodes, 4 * nodes.size()) != hipSuccess ||
+            hipMalloc(&s->prof_off, 4 * off.size()) != hipSuccess ||
+            hipMalloc(&s->prof_out, 8 * (size_t)(2 * nbins)) != hipSuccess) {
+            free_profile(s);
+            set_error("sel_radial_profile: allocation of the bin lists failed");
+            return SEL_ENOMEM;
+        }
+        if (hipMemcpyAsync(s->prof_nodes, nodes.data(), 4 * nodes.size(), hipMemcpyHostToDevice, s->stream) !=
+                hipSuccess ||
+            hipMemcpyAsync(s->prof_off, off.data(), 4 * off.size(), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+            sync_check(s) != SEL_OK) {
+            free_profile(s);
+            set_error("sel_radial_profile: upload of the bin lists failed");
+            return SEL_EDEVICE;
+        }
+        s->prof_nbins = nbins;
+        for (int k = 0; k < 7; ++k) s->prof_key[k] = key[k];
+    }
+    if (int rc = ops_of(s)->axial_terms(s, n, s->io)) return rc;
+    hipLaunchKernelGGL(k_bin_sums, dim3((unsigned)nbins), dim3(256), 0, s->stream, s->io, nl, s->prof_nodes,
+                       s->prof_off, nbins, s->prof_out);
+    if (hipGetLastError() != hipSuccess) {
+        set_error("sel_radial_profile: launch failed");
+        return SEL_EDEVICE;
+    }
+    HIP_OK(hipMemcpyAsync(out, s->prof_out, 8 * (size_t)(2 * nbins), hipMemcpyDeviceToHost, s->stream));
     return sync_check(s);
 }
 

@@ -1417,6 +1417,34 @@ __global__ void k_moments(NodeMap M, const T *f, double rho0, double *rho, doubl
     for (int c = 0; c < DIM; ++c) u[q * DIM + c] = j[c] / r;
 }
 
+// per element node: wJ (u . n) and wJ (u = sum e f / rho, Eq. momentum) for
+// the radial profile diagnostic, FP64 [2][E][np]
+template <int DIM, int Q, typename T, bool DEV>
+__global__ void k_axial_terms(NodeMap M, const T *f, const double *wJ, double rho0, double n0, double n1,
+                              double n2, double *out)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nl = M.E * M.NP;
+    if (q >= nl) return;
+    const int64_t e = q / M.NP;
+    const int p = (int)(q - e * M.NP);
+    bool own;
+    const SIdx si = M.sidx(e, p, own);
+    double m = 0, j[3] = {0, 0, 0};
+    static_for<0, Q>([&](auto AA) {
+        constexpr int a = decltype(AA)::value;
+        const double v = double(f[si.base + (int64_t)a * si.stride]);
+        m += v;
+        if constexpr (lat_e<DIM, Q>(a, 0) != 0) j[0] += lat_e<DIM, Q>(a, 0) * v;
+        if constexpr (lat_e<DIM, Q>(a, 1) != 0) j[1] += lat_e<DIM, Q>(a, 1) * v;
+        if constexpr (lat_e<DIM, Q>(a, 2) != 0) j[2] += lat_e<DIM, Q>(a, 2) * v;
+    });
+    const double r = DEV ? rho0 + m : m;
+    const double un = (j[0] * n0 + j[1] * n1 + j[2] * n2) / r;
+    out[q] = wJ[q] * un;
+    out[nl + q] = wJ[q];
+}
+
 // FP64 integrals with the lumped mass and a non-finite count; per-block
 // partial sums in fixed order, summed by k_reduce_final.
 template <int DIM, int Q, typename T, bool DEV>

@@ -481,10 +481,21 @@ struct Impl {
         return SEL_OK;
     }
 
+    // wJ (u . n) and wJ at every element node, FP64 [2][E][np] (device)
+    static int axial_terms(sel_sim *s, const double *n, double *d_out)
+    {
+        const int64_t nl = s->E * NP;
+        hipLaunchKernelGGL((k_axial_terms<DIM, Q, T, DEV>), dim3((unsigned)((nl + 255) / 256)), dim3(256), 0,
+                           s->stream, nodemap(s), st(s, s->cur), s->wJ, s->p.rho0, n[0], n[1], DIM == 3 ? n[2] : 0.0,
+                           d_out);
+        SEL_LAUNCH_CHECK();
+        return SEL_OK;
+    }
+
     static const Ops *ops()
     {
         static const Ops o = {geometry, mass, init,    step,     moments,  reduce,   scatter,
-                              gather,   apply, features, set_force, grad_row};
+                              gather,   apply, features, set_force, grad_row, axial_terms};
         return &o;
     }
 };

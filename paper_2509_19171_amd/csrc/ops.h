@@ -18,6 +18,7 @@ struct Ops {
     int (*features)(sel_sim *, float *, int owner_out, int filter);
     int (*set_force)(sel_sim *, const double *d_F);  // d_F: device FP64 [E][np][dim]
     int (*grad_row)(sel_sim *, int c, double *d_out);  // du_c/dx_q, FP64 [E][np][dim]
+    int (*axial_terms)(sel_sim *, const double *n, double *d_out);  // wJ u.n and wJ, FP64 [2][E][np]
 };
 
 // learned-closure inference on the simulation's feature rows (closure.hip)

@@ -128,6 +128,14 @@ struct sel_sim {
     float *cl_params = nullptr; // [closure blob]
     float *cl_X = nullptr;      // [Gtot][6] features per node id
     float *cl_dtau = nullptr;   // [Gtot]
+    // radial profile diagnostic (sel_radial_profile): element nodes grouped by
+    // radial bin in ascending order (CSR), built on the first call for a
+    // binning and kept until the binning changes or the simulation ends
+    int32_t *prof_nodes = nullptr;  // [entries] local node indices e * np + p
+    int32_t *prof_off = nullptr;    // [nbins + 1]
+    double *prof_out = nullptr;     // [2 nbins] per-bin sums
+    int prof_nbins = 0;
+    double prof_key[7] = {};        // origin, unit axis, rmax of the current binning
     // optional per-launch timing (sel_step_timed)
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> *timing = nullptr;
 };

@@ -78,6 +78,7 @@ def load():
         "sel_set_force": [P, P],
         "sel_velocity_gradient": [P, P],
         "sel_get_time": [P, P, P],
+        "sel_radial_profile": [P, P, P, ctypes.c_double, I32, P],
         "sel_apply": [P, I32, P, P],
         "sel_geometry": [P, P, P],
         "sel_destroy": [P],
@@ -276,6 +277,18 @@ class Sim:
         out = np.zeros((self.E, self.np_, self.dim, self.dim))
         _check(self._lib.sel_velocity_gradient(self._h, _ptr(out)))
         return out
+
+    def radial_profile(self, origin, axis, rmax, nbins):
+        """Per radial bin of [0, rmax) around the line through origin along
+        axis: (sum wJ u.n, sum wJ) over the element nodes of the bin
+        (sel_radial_profile); their ratio is the bin's mean axial velocity."""
+        o = np.zeros(self.dim)
+        n = np.zeros(self.dim)
+        o[:] = np.asarray(origin, dtype=np.float64)[:self.dim]
+        n[:] = np.asarray(axis, dtype=np.float64)[:self.dim]
+        out = np.zeros(2 * int(nbins))
+        _check(self._lib.sel_radial_profile(self._h, _ptr(o), _ptr(n), float(rmax), int(nbins), _ptr(out)))
+        return out[:nbins], out[nbins:]
 
     def set_force(self, F):
         """Force density per node [E][np][dim] added to rho g from the next

@@ -121,3 +121,33 @@ def test_pipe_wall_shear_laminar():
     tau = -dudr[wall].mean()
     say(f"  -du_z/dr at the wall: {tau:.6e} (4 u_b / R = {4 * c.meta['ub']:.6e})")
     assert abs(tau - 4 * c.meta["ub"]) < 1e-3 * 4 * c.meta["ub"]
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32dev", 1e-5)])
+def test_radial_profile_parity(prec, tol):
+    """sel_radial_profile (the pipe's averaged axial velocity profile, Sec.
+    3.5) against the reference sums on the oracle's state and geometry after
+    20 steps of the perturbed O-grid pipe; bin weights to 1e-12, velocity sums
+    normwise to the storage form's tolerance; a repeated call returns the same
+    values bit for bit, and a new binning replaces the old one."""
+    import oracle
+    from paper_2509_19171_amd import sel
+    from radial_ref import radial_sums
+
+    c = I.case_pipe(N=5, nsq=4, nrad=3, nax=3, L=3.0)
+    g = sel.from_case(c, prec)
+    o = oracle.from_case(c)
+    g.step(20)
+    o.step(20)
+    wJ, _, _ = o.geometry()
+    _, ou = o.moments()
+    R = c.meta["R"] * (1 + 1e-9)
+    for nb in (24, 7):
+        s, w = g.radial_profile((0, 0, 0), (0, 0, 1), R, nb)
+        rs, rw = radial_sums(c.mesh.xyz, wJ, ou, (0, 0, 0), (0, 0, 1), R, nb)
+        es = np.abs(s - rs).max() / np.abs(rs).max()
+        ew = np.abs(w - rw).max() / np.abs(rw).max()
+        say(f"  {prec} nbins {nb}: sums {es:.2e} weights {ew:.2e}; profile {np.round(s / w, 5)}")
+        assert ew < 1e-12 and es < tol
+        s2, w2 = g.radial_profile((0, 0, 0), (0, 0, 1), R, nb)
+        assert np.array_equal(s, s2) and np.array_equal(w, w2)
