@@ -48,19 +48,36 @@ class Samples:
     times: List[float] = field(default_factory=list)
 
 
+def _advance(sims, n: int, force=None, force_every: int = 5):
+    """Step every (case, sim) pair n steps; with force(case, t) -> [E][np][dim],
+    the force density is set again every force_every steps (sel_set_force)."""
+    if force is None:
+        for _, s in sims:
+            s.step(n)
+        return
+    done = 0
+    while done < n:
+        k = min(force_every, n - done)
+        for c, s in sims:
+            s.set_force(force(c, s.time))
+            s.step(k)
+        done += k
+
+
 def generate(make_case, Nf: int, Nc: int, nsnap: int, every: int, warm: int = 0, precision: str = "fp32dev",
-             device: str = "cuda:0") -> Samples:
+             device: str = "cuda:0", force=None, force_every: int = 5) -> Samples:
     """Features and targets from nsnap snapshots of a fine plain run, taken
-    every ``every`` steps after ``warm`` steps."""
+    every ``every`` steps after ``warm`` steps (force: optional time-dependent
+    force density per node, set every force_every steps)."""
     torch = _torch()
     cf, cc = coarse_pair(make_case, Nf, Nc)
     fine = sel.from_case(cf, precision=precision, device=device)
     coarse = sel.from_case(cc, precision=precision, device=device)
     Xs, ys, times = [], [], []
     if warm:
-        fine.step(warm)
+        _advance([(cf, fine)], warm, force, force_every)
     for _ in range(nsnap):
-        fine.step(every)
+        _advance([(cf, fine)], every, force, force_every)
         fine.sync()  # raises on a non-finite state
         sel.coarse_grain(fine, coarse)
         Xs.append(coarse.closure_features().reshape(-1, 6))
@@ -119,6 +136,17 @@ class Judgement:
     ke_ref: List[float]
     ke_plain: List[float]
     ke_closure: List[float]
+    # averaged axial velocity profile (sel_radial_profile), when asked for
+    prof_ref: List[np.ndarray] = field(default_factory=list)
+    prof_plain: List[np.ndarray] = field(default_factory=list)
+    prof_closure: List[np.ndarray] = field(default_factory=list)
+
+    @property
+    def gain_profile(self) -> float:
+        """Mean relative error of the averaged profile, plain over closure."""
+        ep = [np.linalg.norm(p - r) / np.linalg.norm(r) for p, r in zip(self.prof_plain, self.prof_ref)]
+        ec = [np.linalg.norm(p - r) / np.linalg.norm(r) for p, r in zip(self.prof_closure, self.prof_ref)]
+        return float(np.mean(ep) / max(np.mean(ec), 1e-300))
 
     @property
     def gain(self) -> float:
@@ -141,10 +169,12 @@ def _l2(u, uref, wJ):
 
 
 def judge(make_case, Nf: int, Nc: int, blob, nchk: int, every: int, precision: str = "fp32dev",
-          device: str = "cuda:0") -> Judgement:
+          device: str = "cuda:0", force=None, force_every: int = 5, profile=None) -> Judgement:
     """Coarse runs with and without the closure against the coarse-grained
     fine run, compared every ``every`` steps (relative wJ-weighted L2 error of
-    u, and kinetic energy)."""
+    u, and kinetic energy; with profile = (origin, axis, rmax, nbins) also the
+    averaged axial velocity profile). force: optional time-dependent force
+    density per node of every run, set every force_every steps."""
     cf, cc = coarse_pair(make_case, Nf, Nc)
     fine = sel.from_case(cf, precision=precision, device=device)
     ref = sel.from_case(cc, precision=precision, device=device)
@@ -156,9 +186,7 @@ def judge(make_case, Nf: int, Nc: int, blob, nchk: int, every: int, precision: s
     dim = cc.dim
     J = Judgement([], [], [], [], [], [])
     for _ in range(nchk):
-        fine.step(every)
-        plain.step(every)
-        clos.step(every)
+        _advance([(cf, fine), (cc, plain), (cc, clos)], every, force, force_every)
         sel.coarse_grain(fine, ref)
         _, ur = ref.moments()
         _, up = plain.moments()
@@ -169,4 +197,8 @@ def judge(make_case, Nf: int, Nc: int, blob, nchk: int, every: int, precision: s
         J.ke_ref.append(float(ref.reduce()[dim + 1]))
         J.ke_plain.append(float(plain.reduce()[dim + 1]))
         J.ke_closure.append(float(clos.reduce()[dim + 1]))
+        if profile is not None:
+            for sim, lst in ((ref, J.prof_ref), (plain, J.prof_plain), (clos, J.prof_closure)):
+                s_un, s_w = sim.radial_profile(*profile)
+                lst.append(s_un / np.where(s_w > 0, s_w, 1.0))
     return J

@@ -83,7 +83,7 @@ def test_pipe_case_parameters():
     assert abs(c.meta["utau"] - ut) < 1e-15
     assert abs(c.nu - ut / 180) < 1e-18
     assert abs(c.g[2] - 2 * ut * ut) < 1e-18
-    assert c.Q == 27 and c.filter == "exp"
+    assert c.Q == 27 and c.filter == "quad" and c.filter_kc == 2 and c.filter_amp == 0.1
     # u_z at the wall is zero, maximum near 2 u_b on the axis
     r = np.hypot(c.xyz[..., 0], c.xyz[..., 1])
     assert np.abs(c.u[r > 1 - 1e-12]).max() < 1e-12
