@@ -121,6 +121,18 @@ __device__ __forceinline__ int64_t xcd_block(int64_t nblk)
 inline int64_t xcd_grid(int64_t nblk) { return 8 * ((nblk + 7) / 8); }
 
 // --------------------------------------------------------- local physics --
+// e . x over the nonzero components of a lattice velocity (each +-1, so the
+// products are exact): no additions of zero terms.
+template <int ex, int ey, int ez, typename T>
+__device__ __forceinline__ T edot(T x, T y, T z)
+{
+    T r = T(0);
+    if constexpr (ex != 0) r = T(ex) * x;
+    if constexpr (ey != 0) r = (ex != 0) ? r + T(ey) * y : T(ey) * y;
+    if constexpr (ez != 0) r = (ex != 0 || ey != 0) ? r + T(ez) * z : T(ez) * z;
+    return r;
+}
+
 // BGK collision with the higher-order force F** (Sec. 2.1): from the node's
 // values v[a] (full f, or the deviation g = f - t_a rho0 when DEV) compute
 // rho, u = sum e f / rho, F = rho g and
@@ -167,21 +179,24 @@ __device__ __forceinline__ void collide_node(T (&v)[Q], T rho0, T omega, T dt, c
         // arithmetic; its computed moments are sums of small numbers, so
         // they are accurate, and they are projected out before relaxing:
         //   n' = n - t (S0 + e.S1 / cs2), f* = f-bar-eq + dt F** + (1 - omega) n + omega (n - n').
+        // Dot products with e_a take only its nonzero components (+-1), and
+        // the weight's products t m0, t rho, omega t are formed once per weight.
         T base[Q];
         T S0 = 0, S1x = 0, S1y = 0, S1z = 0;
         // without a body force F** vanishes: the same values without its terms
         const bool forced = (g[0] != T(0)) | (g[1] != T(0)) | (g[2] != T(0));
+        const T c3uu = c3 * uu;
         auto pass1 = [&](auto FORCED) {
             static_for<0, Q>([&](auto A) {
                 constexpr int a = decltype(A)::value;
                 constexpr int ex = lat_e<DIM, Q>(a, 0), ey = lat_e<DIM, Q>(a, 1), ez = lat_e<DIM, Q>(a, 2);
                 const T t = T(lat_t<DIM, Q>(a));
-                const T eu = T(ex) * u0 + T(ey) * u1 + T(ez) * u2;
-                const T poly = c1 * eu + c2 * eu * eu - c3 * uu;
-                const T feq = DEV ? t * (m0 + rho * poly) : t * rho * (T(1) + poly);
+                const T eu = edot<ex, ey, ez>(u0, u1, u2);
+                const T poly = eu * (c1 + c2 * eu) - c3uu;  // e.u/cs2 + (e.u)^2/(2 cs4) - u.u/(2 cs2)
+                const T feq = DEV ? (t * m0 + (t * rho) * poly) : (t * rho) * (T(1) + poly);
                 T fbeq = feq;
                 if constexpr (decltype(FORCED)::value) {
-                    const T eF = T(ex) * F0 + T(ey) * F1 + T(ez) * F2;
+                    const T eF = edot<ex, ey, ez>(F0, F1, F2);
                     const T fss = t * (T(9) * eu * eF - T(3) * uF);
                     fbeq = feq - half_dt * fss;
                     base[a] = fbeq + dt * fss;
@@ -199,15 +214,13 @@ __device__ __forceinline__ void collide_node(T (&v)[Q], T rho0, T omega, T dt, c
         if (forced) pass1(std::true_type{});
         else pass1(std::false_type{});
         const T keep = T(1) - omega;
+        const T S3x = T(3) * S1x, S3y = T(3) * S1y, S3z = T(3) * S1z;
         static_for<0, Q>([&](auto A) {
             constexpr int a = decltype(A)::value;
             constexpr int ex = lat_e<DIM, Q>(a, 0), ey = lat_e<DIM, Q>(a, 1), ez = lat_e<DIM, Q>(a, 2);
             const T t = T(lat_t<DIM, Q>(a));
-            T es = S0;
-            if constexpr (ex != 0) es += T(3 * ex) * S1x;
-            if constexpr (ey != 0) es += T(3 * ey) * S1y;
-            if constexpr (ez != 0) es += T(3 * ez) * S1z;
-            v[a] = base[a] + (keep * v[a] + omega * (t * es));
+            const T es = S0 + edot<ex, ey, ez>(S3x, S3y, S3z);
+            v[a] = base[a] + (keep * v[a] + (omega * t) * es);
         });
     }
     rho_out = rho;
