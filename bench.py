@@ -374,8 +374,8 @@ def main():
             if "stage23" in counters and "assembly" in counters:
                 traffic = int(counters["stage23"] + counters["assembly"])
     roof = {"bound": "hbm",
-            "kernel": "later SSPRK stage: k_stage element kernel (streaming, wall flux, interior update) + "
-                      "k_group_split shared-node assembly",
+            "kernel": "later SSPRK stage: element kernel (k_stage23_mf for FP32 3D order 7, else k_stage: "
+                      "streaming, wall flux, interior update) + k_group_split shared-node assembly",
             "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4),
             "traffic": traffic,
             "algorithmic_bytes_per_launch": int(stage_bytes),
