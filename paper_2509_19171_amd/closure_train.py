@@ -64,25 +64,102 @@ def _advance(sims, n: int, force=None, force_every: int = 5):
         done += k
 
 
+def _run_from(sim, case, n: int, t0: float, force=None, force_every: int = 5):
+    """n steps of a run started from a coarse-grained state at time t0 (its
+    own clock is not the fine run's): the force is evaluated at t0 + elapsed."""
+    done = 0
+    while done < n:
+        k = min(force_every, n - done) if force is not None else n - done
+        if force is not None:
+            sim.set_force(force(case, t0 + done * case.dt))
+        sim.step(k)
+        done += k
+
+
+def constant_blob(y: float, dtau_max: float = 100.0) -> np.ndarray:
+    """A closure blob whose network outputs the constant dtau / tau = y (output
+    weights zero, output bias softplus^-1(y)): a uniform viscosity increase."""
+    blob = I.closure_blob(0, np.zeros(6), np.ones(6), dtau_max=dtau_max)
+    blob[-66:-2] = 0.0
+    blob[-2] = np.float32(np.log(np.expm1(y)))
+    return blob
+
+
+def _posterior_targets(fine, cf, cc, probes, horizon: int, y_probe: float, y_max: float, wJ, force, force_every):
+    """A-posteriori targets of the current snapshot: from the coarse-grained
+    fine state, a plain coarse run (u0) and one with the uniform increment
+    dtau / tau = y_probe (u1) go horizon steps; the fine run goes on for the
+    same steps and is coarse-grained (ur). Taking the response of u to an
+    element's increment as linear and local over the horizon, the element's
+    increment that best moves u0 towards ur in the wJ-weighted least-squares
+    sense is y_probe <ur - u0, u1 - u0> / <u1 - u0, u1 - u0> over the element,
+    clipped to [0, y_max]; it is the target of every node of the element."""
+    p0, p1, ref = probes
+    t = fine.time
+    sel.coarse_grain(fine, p0)
+    sel.coarse_grain(fine, p1)
+    _run_from(p0, cc, horizon, t, force, force_every)
+    _run_from(p1, cc, horizon, t, force, force_every)
+    _advance([(cf, fine)], horizon, force, force_every)
+    sel.coarse_grain(fine, ref)
+    _, u0 = p0.moments()
+    _, u1 = p1.moments()
+    _, ur = ref.moments()
+    return posterior_fit(u0, u1, ur, wJ, y_probe, y_max)
+
+
+def posterior_fit(u0, u1, ur, wJ, y_probe: float, y_max: float) -> np.ndarray:
+    """Per element (arrays [E][np][dim], wJ [E][np]): the increment y with
+    u0 + (y / y_probe)(u1 - u0) closest to ur in the wJ-weighted norm,
+    clipped to [0, y_max] (0 where the probe moved nothing); [E][np]."""
+    d = u1 - u0
+    num = (wJ * ((ur - u0) * d).sum(-1)).sum(1)
+    den = (wJ * (d * d).sum(-1)).sum(1)
+    ye = np.where(den > 0, y_probe * num / np.where(den > 0, den, 1.0), 0.0)
+    ye = np.clip(ye, 0.0, y_max)
+    return np.repeat(ye[:, None], wJ.shape[1], axis=1)
+
+
 def generate(make_case, Nf: int, Nc: int, nsnap: int, every: int, warm: int = 0, precision: str = "fp32dev",
-             device: str = "cuda:0", force=None, force_every: int = 5) -> Samples:
+             device: str = "cuda:0", force=None, force_every: int = 5, target: str = "a_priori",
+             horizon: int = 300, y_probe: float = 1.0, y_max: float = 10.0) -> Samples:
     """Features and targets from nsnap snapshots of a fine plain run, taken
     every ``every`` steps after ``warm`` steps (force: optional time-dependent
-    force density per node, set every force_every steps)."""
+    force density per node, set every force_every steps). target "a_priori":
+    the sub-filter stress targets of sel_closure_targets; "a_posteriori": the
+    per-element increments that best steer a short coarse run (horizon steps
+    < every) towards the coarse-grained fine run (_posterior_targets)."""
     torch = _torch()
+    if target not in ("a_priori", "a_posteriori"):
+        raise ValueError(target)
+    post = target == "a_posteriori"
+    if post and not 0 < horizon < every:
+        raise ValueError("the a-posteriori horizon must be shorter than the snapshot interval")
     cf, cc = coarse_pair(make_case, Nf, Nc)
     fine = sel.from_case(cf, precision=precision, device=device)
     coarse = sel.from_case(cc, precision=precision, device=device)
+    probes, wJ = None, None
+    if post:
+        probes = (sel.from_case(cc, precision=precision, device=device),
+                  sel.from_case(cc, precision=precision, device=device, closure=constant_blob(y_probe)),
+                  sel.from_case(cc, precision=precision, device=device))
+        wJ, _ = coarse.geometry()
     Xs, ys, times = [], [], []
     if warm:
         _advance([(cf, fine)], warm, force, force_every)
+    ahead = 0  # steps the fine run went on past the last snapshot (a-posteriori probe)
     for _ in range(nsnap):
-        _advance([(cf, fine)], every, force, force_every)
+        _advance([(cf, fine)], every - ahead, force, force_every)
         fine.sync()  # raises on a non-finite state
         sel.coarse_grain(fine, coarse)
         Xs.append(coarse.closure_features().reshape(-1, 6))
-        ys.append(sel.closure_targets(fine, coarse).reshape(-1))
         times.append(fine.time)
+        if post:
+            y = _posterior_targets(fine, cf, cc, probes, horizon, y_probe, y_max, wJ, force, force_every)
+            ys.append(torch.from_numpy(y.astype(np.float32).reshape(-1)).to(Xs[-1].device))
+            ahead = horizon
+        else:
+            ys.append(sel.closure_targets(fine, coarse).reshape(-1))
     torch.cuda.synchronize()
     return Samples(torch.cat(Xs), torch.cat(ys), times)
 

@@ -20,7 +20,19 @@ coarse runs' own error (0.19% on u_z(r) at the end, 0.68% on u) comes from the
 wall layer's resolution at order 5, which a non-negative eddy viscosity cannot
 remove. The test asserts exactly that: the closure run stays finite, its
 increments stay small and non-negative, and it neither gains nor loses more
-than 0.1% against the plain run."""
+than 0.1% against the plain run.
+
+The second test trains on a-posteriori targets instead (closure_train,
+target "a_posteriori"): at each snapshot a plain coarse run and one with a
+uniform increment dtau/tau = 1 go 300 steps from the coarse-grained fine
+state, and each element's target is the increment that best steers the plain
+run's velocity towards the coarse-grained fine run over those steps (linear,
+local response; clipped to [0, 10]). Measured on MI355X: the kinetic-energy
+error falls 3.37x (the plain coarse run keeps too much energy and the learned
+viscosity removes it), the velocity L2 error 1.004x, while the u_z(r) error
+grows slightly (gain 0.960: the extra viscosity also acts in the wall layer,
+whose error is one of resolution). Asserted with margins: KE gain > 2.5,
+velocity gain > 0.99, u_z(r) gain in (0.93, 1.0)."""
 import math
 import sys
 
@@ -62,15 +74,15 @@ def _force(meta, dt):
     return force
 
 
-def test_closure_gain_pipe():
-    assert torch.cuda.is_available()
+def _judge(target):
     from paper_2509_19171_amd import closure_train as T
 
     cf = _make(180)(7)
     force = _force(cf.meta, cf.dt)
     every = TOTAL // NCHK
-    say(f"pipe judge: E={cf.E}, dt {cf.dt:.4g}, {TOTAL} fine steps, snapshots every {every}")
-    S = [T.generate(_make(seed), 7, 5, NCHK, every, force=force, force_every=20) for seed in (181, 182)]
+    say(f"pipe judge ({target} targets): E={cf.E}, dt {cf.dt:.4g}, {TOTAL} fine steps, snapshots every {every}")
+    S = [T.generate(_make(seed), 7, 5, NCHK, every, force=force, force_every=20, target=target, horizon=300,
+                    y_probe=1.0, y_max=10.0) for seed in (181, 182)]
     X = torch.cat([s.X for s in S])
     y = torch.cat([s.y for s in S])
     say(f"  {X.shape[0]} samples, mean target {float(y.mean()):.3e}, max {float(y.max()):.3e}")
@@ -93,7 +105,22 @@ def test_closure_gain_pipe():
     say("  u_z(r)/u_b plain   " + " ".join(f"{v:.4f}" for v in J.prof_plain[-1] / ub))
     say("  u_z(r)/u_b closure " + " ".join(f"{v:.4f}" for v in J.prof_closure[-1] / ub))
     say(f"  gain: u_z(r) {J.gain_profile:.5f}, velocity L2 {J.gain:.5f}, kinetic energy {J.gain_ke:.5f}")
-    for g in (J.gain_profile, J.gain, J.gain_ke):
-        assert 0.999 < g < 1.001
     # the coarse runs follow the reference: profile error below 0.5%
     assert max(np.linalg.norm(p - r) / np.linalg.norm(r) for p, r in zip(J.prof_plain, J.prof_ref)) < 5e-3
+    assert all(np.isfinite(J.err_closure))
+    return J
+
+
+def test_closure_gain_pipe():
+    assert torch.cuda.is_available()
+    J = _judge("a_priori")
+    for g in (J.gain_profile, J.gain, J.gain_ke):
+        assert 0.999 < g < 1.001
+
+
+def test_closure_gain_pipe_a_posteriori():
+    assert torch.cuda.is_available()
+    J = _judge("a_posteriori")
+    assert J.gain_ke > 2.5
+    assert J.gain > 0.99
+    assert 0.93 < J.gain_profile < 1.0
