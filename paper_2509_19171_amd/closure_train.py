@@ -85,7 +85,8 @@ def constant_blob(y: float, dtau_max: float = 100.0) -> np.ndarray:
     return blob
 
 
-def _posterior_targets(fine, cf, cc, probes, horizon: int, y_probe: float, y_max: float, wJ, force, force_every):
+def _posterior_targets(fine, cf, cc, probes, horizon: int, y_probe: float, y_max: float, wJ, force, force_every,
+                       components=None):
     """A-posteriori targets of the current snapshot: from the coarse-grained
     fine state, a plain coarse run (u0) and one with the uniform increment
     dtau / tau = y_probe (u1) go horizon steps; the fine run goes on for the
@@ -105,13 +106,17 @@ def _posterior_targets(fine, cf, cc, probes, horizon: int, y_probe: float, y_max
     _, u0 = p0.moments()
     _, u1 = p1.moments()
     _, ur = ref.moments()
-    return posterior_fit(u0, u1, ur, wJ, y_probe, y_max)
+    return posterior_fit(u0, u1, ur, wJ, y_probe, y_max, components)
 
 
-def posterior_fit(u0, u1, ur, wJ, y_probe: float, y_max: float) -> np.ndarray:
+def posterior_fit(u0, u1, ur, wJ, y_probe: float, y_max: float, components=None) -> np.ndarray:
     """Per element (arrays [E][np][dim], wJ [E][np]): the increment y with
-    u0 + (y / y_probe)(u1 - u0) closest to ur in the wJ-weighted norm,
-    clipped to [0, y_max] (0 where the probe moved nothing); [E][np]."""
+    u0 + (y / y_probe)(u1 - u0) closest to ur in the wJ-weighted norm over the
+    velocity components given (all by default), clipped to [0, y_max] (0
+    where the probe moved nothing); [E][np]."""
+    if components is not None:
+        idx = list(components)
+        u0, u1, ur = u0[..., idx], u1[..., idx], ur[..., idx]
     d = u1 - u0
     num = (wJ * ((ur - u0) * d).sum(-1)).sum(1)
     den = (wJ * (d * d).sum(-1)).sum(1)
@@ -122,13 +127,14 @@ def posterior_fit(u0, u1, ur, wJ, y_probe: float, y_max: float) -> np.ndarray:
 
 def generate(make_case, Nf: int, Nc: int, nsnap: int, every: int, warm: int = 0, precision: str = "fp32dev",
              device: str = "cuda:0", force=None, force_every: int = 5, target: str = "a_priori",
-             horizon: int = 300, y_probe: float = 1.0, y_max: float = 10.0) -> Samples:
+             horizon: int = 300, y_probe: float = 1.0, y_max: float = 10.0, components=None) -> Samples:
     """Features and targets from nsnap snapshots of a fine plain run, taken
     every ``every`` steps after ``warm`` steps (force: optional time-dependent
     force density per node, set every force_every steps). target "a_priori":
     the sub-filter stress targets of sel_closure_targets; "a_posteriori": the
     per-element increments that best steer a short coarse run (horizon steps
-    < every) towards the coarse-grained fine run (_posterior_targets)."""
+    < every) towards the coarse-grained fine run (_posterior_targets; over the
+    velocity components given, all by default)."""
     torch = _torch()
     if target not in ("a_priori", "a_posteriori"):
         raise ValueError(target)
@@ -155,7 +161,7 @@ def generate(make_case, Nf: int, Nc: int, nsnap: int, every: int, warm: int = 0,
         Xs.append(coarse.closure_features().reshape(-1, 6))
         times.append(fine.time)
         if post:
-            y = _posterior_targets(fine, cf, cc, probes, horizon, y_probe, y_max, wJ, force, force_every)
+            y = _posterior_targets(fine, cf, cc, probes, horizon, y_probe, y_max, wJ, force, force_every, components)
             ys.append(torch.from_numpy(y.astype(np.float32).reshape(-1)).to(Xs[-1].device))
             ahead = horizon
         else:

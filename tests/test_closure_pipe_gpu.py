@@ -26,13 +26,13 @@ The second test trains on a-posteriori targets instead (closure_train,
 target "a_posteriori"): at each snapshot a plain coarse run and one with a
 uniform increment dtau/tau = 1 go 300 steps from the coarse-grained fine
 state, and each element's target is the increment that best steers the plain
-run's velocity towards the coarse-grained fine run over those steps (linear,
-local response; clipped to [0, 10]). Measured on MI355X: the kinetic-energy
-error falls 3.37x (the plain coarse run keeps too much energy and the learned
-viscosity removes it), the velocity L2 error 1.004x, while the u_z(r) error
-grows slightly (gain 0.960: the extra viscosity also acts in the wall layer,
-whose error is one of resolution). Asserted with margins: KE gain > 2.5,
-velocity gain > 0.99, u_z(r) gain in (0.93, 1.0)."""
+run's axial velocity towards the coarse-grained fine run over those steps
+(linear, local response; clipped to [0, 10]). Measured on MI355X: the u_z(r)
+error falls 1.029x, the velocity L2 error 1.008x and the kinetic-energy error
+9.99x (the plain coarse run keeps too much energy). Fitting all three
+velocity components instead gives 0.960 / 1.004 / 3.37, and a 600-step
+horizon 0.90-0.91 on u_z(r) (the linear response no longer holds). Asserted
+with margins: u_z(r) gain > 1.01, velocity gain > 1.0, KE gain > 5."""
 import math
 import sys
 
@@ -82,7 +82,7 @@ def _judge(target):
     every = TOTAL // NCHK
     say(f"pipe judge ({target} targets): E={cf.E}, dt {cf.dt:.4g}, {TOTAL} fine steps, snapshots every {every}")
     S = [T.generate(_make(seed), 7, 5, NCHK, every, force=force, force_every=20, target=target, horizon=300,
-                    y_probe=1.0, y_max=10.0) for seed in (181, 182)]
+                    y_probe=1.0, y_max=10.0, components=(2,)) for seed in (181, 182)]
     X = torch.cat([s.X for s in S])
     y = torch.cat([s.y for s in S])
     say(f"  {X.shape[0]} samples, mean target {float(y.mean()):.3e}, max {float(y.max()):.3e}")
@@ -121,6 +121,6 @@ def test_closure_gain_pipe():
 def test_closure_gain_pipe_a_posteriori():
     assert torch.cuda.is_available()
     J = _judge("a_posteriori")
-    assert J.gain_ke > 2.5
-    assert J.gain > 0.99
-    assert 0.93 < J.gain_profile < 1.0
+    assert J.gain_profile > 1.01
+    assert J.gain > 1.0
+    assert J.gain_ke > 5.0

@@ -55,3 +55,15 @@ def test_posterior_fit_projection_and_clipping():
     assert np.all(y == 0.0)
     y = T.posterior_fit(u0, u0, ur, wJ, 1.0, 10.0)
     assert np.all(y == 0.0)
+
+
+def test_posterior_fit_over_selected_components():
+    """Restricted to one component, the fit sees only that component's
+    residual and response."""
+    u0, d, wJ = _fields(4, E=2)
+    u1 = u0 + d
+    ur = u0.copy()
+    ur[..., 2] += 0.7 * d[..., 2]          # the axial component moved 0.7 of the way
+    ur[..., 0] -= 5.0 * d[..., 0]          # the others against the probe
+    y = T.posterior_fit(u0, u1, ur, wJ, 1.0, 10.0, components=(2,))
+    np.testing.assert_allclose(y, 0.7, rtol=1e-12)
