@@ -932,7 +932,13 @@ template <int Q, typename T, int DGN = 0>
 __global__ void __launch_bounds__(256) k_group_split(GroupArgs<T> A)
 {
     const int w = threadIdx.x >> 6;
-    const int64_t g = (int64_t)blockIdx.x * 128 + (w >> 1) * 64 + (threadIdx.x & 63);
+    // blocks of 128 groups, a contiguous range of them per XCD: groups are
+    // ordered by owner element, so each XCD assembles the groups of the
+    // elements it streams, and the next stage finds them in its own L2
+    const int64_t nb = (A.ngrp + 127) / 128;
+    const int64_t gb = xcd_block(nb);
+    if (gb >= nb) return;  // whole workgroup
+    const int64_t g = gb * 128 + (w >> 1) * 64 + (threadIdx.x & 63);
     if (g >= A.ngrp) return;
     const int nm = A.goff[g + 1] - A.goff[g];
     const int64_t h = (nm > 2) ? (int64_t)A.hidx[g] : 0;

@@ -149,7 +149,7 @@ struct Impl {
         if (int rc = tic(s, 2, ev)) return rc;
         // the discontinuous coupling adds its interface flux here
         // 128 groups per workgroup, two wavefronts per group
-        dim3 grid2((unsigned)((s->ngrp + 127) / 128));
+        dim3 grid2((unsigned)xcd_grid((s->ngrp + 127) / 128));
         if (B.nbr) {
             hipLaunchKernelGGL((k_group_split<Q, T, N>), grid2, block, 0, s->stream, B);
         } else {
