@@ -5,11 +5,13 @@
 // contributions, with two of the three line contractions on the matrix cores.
 //
 // Memory: the interior block [Q][NI] of the operand and of the post-collision
-// state are read as 16-byte vectors (kept in registers for the update), the
-// boundary nodes velocity by velocity over the element's boundary slots; the
-// moving velocities' planes go to LDS (the rest velocity neither streams nor
-// meets the wall flux). Results go through LDS in global order: the interior
-// update as 16-byte vectors, the boundary contributions slot by slot.
+// state are read as 16-byte vectors (kept in registers for the update); the
+// planes of the moving velocities are filled one slot per thread (threads
+// 0 .. NB-1 the boundary slots, through the slot's node group; the others
+// the interior slots), so that a slot's addresses are computed once (the
+// rest velocity neither streams nor meets the wall flux). Results go through
+// LDS in global order: the interior update as 16-byte vectors, the boundary
+// contributions slot by slot.
 //
 // Contractions: wavefront w holds the k-slice k = w of the element. For each
 // velocity, the slice's 8 r-lines and 8 s-lines are one v_mfma_f32_16x16x4f32
@@ -59,8 +61,7 @@ __global__ void __launch_bounds__(512, 4) k_stage23_mf(StageArgs<float> A)
     constexpr int STG = QM * NI + QM * NB;
     constexpr int PLN = (NPL * NP > STG) ? NPL * NP : STG;
     constexpr int NQ4 = Q * NI / 4;           // float4 of the interior block
-    constexpr int NBV = NPL * NB;             // boundary values loaded
-    constexpr int NBR = (NBV + 511) / 512;
+    static_assert(NB + NI == NP, "one slot per thread");
     constexpr int NPAIR = (QM + 1) / 2;
     __shared__ __attribute__((aligned(16))) float pl[PLN];
     __shared__ float xb[8][2][128];  // per wavefront: r- and s-derivatives of a velocity pair
@@ -96,16 +97,28 @@ __global__ void __launch_bounds__(512, 4) k_stage23_mf(StageArgs<float> A)
             f0v[r] = ok ? __builtin_nontemporal_load(z4 + q) : mf4{0.f, 0.f, 0.f, 0.f};
         }
     }
-    float bv[NBR];
-#pragma unroll
-    for (int r = 0; r < NBR; ++r) {
-        const int q = tid + 512 * r;
-        bv[r] = 0.f;
-        if (q < NBV) {
-            const int a = q / NB + PO, b = q - (q / NB) * NB;
-            const int64_t g = A.bmap[e * NB + b];
-            bv[r] = A.op[A.QGi + (g / kTile) * (int64_t)Q * kTile + (g % kTile) + (int64_t)a * kTile];
-        }
+    // boundary slots one per thread (threads 0 .. NB-1): the slot's group is
+    // looked up once, then its value of every moving velocity is loaded
+    float bv[NPL];
+    int bnode = 0;
+    if (tid < NB) {
+        const int64_t g = A.bmap[e * NB + tid];
+        const float *src = A.op + A.QGi + (g / kTile) * (int64_t)Q * kTile + (g % kTile);
+        bnode = A.bpos[tid];
+        static_for<PO, Q>([&](auto AA) {
+            constexpr int a = decltype(AA)::value;
+            bv[a - PO] = src[a * kTile];
+        });
+    } else if (tid < NB + NI) {
+        // interior slots one per thread as well (the 16-byte vectors above
+        // serve the update)
+        const int s = tid - NB;
+        const float *src = A.op + ib + s;
+        bnode = interior_node(s);
+        static_for<PO, Q>([&](auto AA) {
+            constexpr int a = decltype(AA)::value;
+            bv[a - PO] = src[a * NI];
+        });
     }
     float Gr[3][3];
 #pragma unroll
@@ -126,27 +139,11 @@ __global__ void __launch_bounds__(512, 4) k_stage23_mf(StageArgs<float> A)
         }
     }
     // planes
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-        const int q = tid + 512 * r;
-        if (q < NQ4) {
-            const int a = (4 * q) / NI, s0 = 4 * q - a * NI;
-            if (a >= PO) {
-                float *P = pl + (a - PO) * NP;
-                P[interior_node(s0)] = fkv[r].x;
-                P[interior_node(s0 + 1)] = fkv[r].y;
-                P[interior_node(s0 + 2)] = fkv[r].z;
-                P[interior_node(s0 + 3)] = fkv[r].w;
-            }
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < NBR; ++r) {
-        const int q = tid + 512 * r;
-        if (q < NBV) {
-            const int a = q / NB, b = q - a * NB;
-            pl[a * NP + A.bpos[b]] = bv[r];
-        }
+    if (tid < NB + NI) {
+        static_for<PO, Q>([&](auto AA) {
+            constexpr int a = decltype(AA)::value;
+            pl[(a - PO) * NP + bnode] = bv[a - PO];
+        });
     }
     __syncthreads();
 
