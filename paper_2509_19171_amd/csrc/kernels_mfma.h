@@ -11,7 +11,7 @@
 // the interior slots), so that a slot's addresses are computed once (the
 // rest velocity neither streams nor meets the wall flux). Results go through
 // LDS in global order: the interior update as 16-byte vectors, the boundary
-// contributions slot by slot.
+// contributions one slot per thread.
 //
 // Contractions: wavefront w holds the k-slice k = w of the element. For each
 // velocity, the slice's 8 r-lines and 8 s-lines are one v_mfma_f32_16x16x4f32
@@ -272,13 +272,14 @@ __global__ void __launch_bounds__(512, 4) k_stage23_mf(StageArgs<float> A)
             }
         }
     }
-    // boundary contributions slot by slot
-    {
-        const int32_t *pm = A.posmap + e * NB;
-        for (int q = tid; q < QM * NB; q += 512) {
-            const int a = q / NB, b = q - a * NB;
-            A.rtb[(int64_t)(a + 1) * A.plane + pm[b]] = pl[QM * NI + q];
-        }
+    // boundary contributions one slot per thread: the slot's position in the
+    // rank planes is read once
+    if (tid < NB) {
+        float *dst = A.rtb + A.posmap[e * NB + tid];
+        static_for<1, Q>([&](auto AA) {
+            constexpr int a = decltype(AA)::value;
+            dst[(int64_t)a * A.plane] = pl[QM * NI + (a - 1) * NB + tid];
+        });
     }
 }
 
