@@ -415,7 +415,7 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK), (((MODE == M_STAGE23 || 
     constexpr bool STG = FULL && (MODE == M_STAGE23 || MODE == M_STAGE1);
     constexpr int PL_N = (ALLQ ? 3 : 2) * NA * EPB * NP;
     constexpr int LDS_N = (FULL || FF) ? (ALLQ ? (Q * NP > PL_N ? Q * NP : PL_N) : Q * NP) : PL_N;
-    __shared__ T lds[LDS_N];
+    __shared__ __attribute__((aligned(16))) T lds[LDS_N];
     T(*pl)[EPB * NP] = reinterpret_cast<T(*)[EPB * NP]>(lds);
     __shared__ T sF[ALLQ ? n1 * n1 : 1];
 
@@ -736,38 +736,42 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK), (((MODE == M_STAGE23 || 
             velocity(AA, pl[a], fq[a], f0v);
         });
         if constexpr (STG) {
-            // results go through LDS in global order: the element's interior
-            // block [Q][NI] is one contiguous run, and the boundary
-            // contributions are written slot by slot in face order. The
+            // results go through LDS: the element's interior block [Q][NI]
+            // is stored as one contiguous run, and the boundary
+            // contributions slot by slot in face order. The
             // interior block is written non-temporally (whole lines, not read
             // again in this stage) so that L2 keeps the contribution slots,
             // which neighbouring elements fill line by line, and the shared
             // operand values.
             __syncthreads();  // every plane read done
-            if (inner) {
+            // staging [Q][NP] in slot order (interior slots, then boundary
+            // slots): one store per velocity for every node, whichever kind
+            {
+                const int slot = inner ? pc : NI + bsl;
                 static_for<0, Q>([&](auto AA) {
                     constexpr int a = decltype(AA)::value;
-                    lds[a * NI + pc] = fq[a];
-                });
-            } else {
-                static_for<0, Q>([&](auto AA) {
-                    constexpr int a = decltype(AA)::value;
-                    lds[Q * NI + a * NB + bsl] = fq[a];
+                    lds[a * NP + slot] = fq[a];
                 });
             }
             __syncthreads();
             T *dst = A.out + e * (int64_t)Q * NI;
-            if constexpr ((Q * NI) % 4 == 0) {
+            if constexpr (NI % 4 == 0 && NP % 4 == 0) {
                 typedef T v4 __attribute__((ext_vector_type(4)));
-                for (int q = tid; q < Q * NI / 4; q += GG::BLOCK)
-                    __builtin_nontemporal_store(reinterpret_cast<const v4 *>(lds)[q], reinterpret_cast<v4 *>(dst) + q);
+                for (int q = tid; q < Q * NI / 4; q += GG::BLOCK) {
+                    const int a = (4 * q) / NI, s0 = 4 * q - a * NI;
+                    __builtin_nontemporal_store(*reinterpret_cast<const v4 *>(lds + a * NP + s0),
+                                                reinterpret_cast<v4 *>(dst) + q);
+                }
             } else {
-                for (int q = tid; q < Q * NI; q += GG::BLOCK) dst[q] = lds[q];
+                for (int q = tid; q < Q * NI; q += GG::BLOCK) {
+                    const int a = q / NI;
+                    dst[q] = lds[a * NP + q - a * NI];
+                }
             }
             const int32_t *pm = A.posmap + e * NB;
             for (int q = tid; q < Q * NB; q += GG::BLOCK) {
                 const int a = q / NB, b = q - a * NB;
-                A.rtb[(int64_t)a * A.plane + pm[b]] = lds[Q * NI + q];
+                A.rtb[(int64_t)a * A.plane + pm[b]] = lds[a * NP + NI + b];
             }
         }
     } else {

@@ -10,7 +10,7 @@
 // 0 .. NB-1 the boundary slots, through the slot's node group; the others
 // the interior slots), so that a slot's addresses are computed once (the
 // rest velocity neither streams nor meets the wall flux). Results go through
-// LDS in global order: the interior update as 16-byte vectors, the boundary
+// LDS in slot order: the interior update as 16-byte vectors, the boundary
 // contributions one slot per thread.
 //
 // Contractions: wavefront w holds the k-slice k = w of the element. For each
@@ -58,7 +58,7 @@ __global__ void __launch_bounds__(512, 4) k_stage23_mf(StageArgs<float> A)
     constexpr int PO = 1;
     constexpr int NPL = Q - PO;
     constexpr int QM = Q - 1;
-    constexpr int STG = QM * NI + QM * NB;
+    constexpr int STG = QM * NP;  // staging [Q-1][NP] in slot order
     constexpr int PLN = (NPL * NP > STG) ? NPL * NP : STG;
     constexpr int NQ4 = Q * NI / 4;           // float4 of the interior block
     static_assert(NB + NI == NP, "one slot per thread");
@@ -229,15 +229,13 @@ __global__ void __launch_bounds__(512, 4) k_stage23_mf(StageArgs<float> A)
 
     // ------------------------------------------------------- stores --
     __syncthreads();  // every plane read done: the planes become the staging area
-    if (inner) {
+    // staging [Q-1][NP] in slot order (interior slots, then boundary slots):
+    // one store per velocity for every node, whichever kind it is
+    {
+        const int slot = inner ? pc : NI + bsl;
         static_for<1, Q>([&](auto AA) {
             constexpr int a = decltype(AA)::value;
-            pl[(a - 1) * NI + pc] = res[a - 1];
-        });
-    } else {
-        static_for<1, Q>([&](auto AA) {
-            constexpr int a = decltype(AA)::value;
-            pl[QM * NI + (a - 1) * NB + bsl] = res[a - 1];
+            pl[(a - 1) * NP + slot] = res[a - 1];
         });
     }
     __syncthreads();
@@ -257,7 +255,7 @@ __global__ void __launch_bounds__(512, 4) k_stage23_mf(StageArgs<float> A)
                 if (a == 0) {
                     L = fs * rh;
                 } else {
-                    const mf4 rt = *reinterpret_cast<const mf4 *>(pl + (a - 1) * NI + s0);
+                    const mf4 rt = *reinterpret_cast<const mf4 *>(pl + (a - 1) * NP + s0);
                     L = rt * iw4[s0 / 4] + fs * rh;
                 }
                 const mf4 fk = fkv[r];
@@ -278,7 +276,7 @@ __global__ void __launch_bounds__(512, 4) k_stage23_mf(StageArgs<float> A)
         float *dst = A.rtb + A.posmap[e * NB + tid];
         static_for<1, Q>([&](auto AA) {
             constexpr int a = decltype(AA)::value;
-            dst[(int64_t)a * A.plane] = pl[QM * NI + (a - 1) * NB + tid];
+            dst[(int64_t)a * A.plane] = pl[(a - 1) * NP + NI + tid];
         });
     }
 }
