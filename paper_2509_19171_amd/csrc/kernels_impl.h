@@ -486,11 +486,45 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK), (((MODE == M_STAGE23 || 
             });
         }
     };
+    // first stage with the filter, one element per workgroup: the element's
+    // values go straight to the planes, one slot per thread (interior slots
+    // contiguous per velocity, boundary slots through their node group)
+    constexpr bool SLOT = FF && FULL && EPB == 1 && MODE == M_STAGE1 && NB + NI == NP;
+    bool slotted = false;
+    if constexpr (SLOT) {
+        if (filt) {
+            slotted = true;
+            const T *src;
+            int node, stride;
+            if (tid < NI) {
+                src = A.op + e * (int64_t)Q * NI + tid;
+                stride = NI;
+                node = (tid % (N - 1) + 1) + n1 * ((tid / (N - 1)) % (N - 1) + 1) + n1 * n1 * (tid / ((N - 1) * (N - 1)) + 1);
+            } else {
+                const int b = tid - NI;
+                const int64_t g = A.bmap[e * NB + b];
+                src = A.op + A.QGi + (g / kTile) * (int64_t)Q * kTile + (g % kTile);
+                stride = kTile;
+                node = A.bpos[b];
+            }
+            T v[Q];
+            static_for<0, Q>([&](auto AA) {
+                constexpr int a = decltype(AA)::value;
+                v[a] = src[a * stride];
+            });
+            static_for<0, Q>([&](auto AA) {
+                constexpr int a = decltype(AA)::value;
+                pl[a][node] = v[a];
+            });
+        }
+    }
     if constexpr (ALLQ || FULL) {
-        static_for<0, Q>([&](auto AA) {
-            constexpr int a = decltype(AA)::value;
-            fq[a] = valid ? A.op[si.base + (int64_t)a * si.stride] : T(0);
-        });
+        if (!slotted) {
+            static_for<0, Q>([&](auto AA) {
+                constexpr int a = decltype(AA)::value;
+                fq[a] = valid ? A.op[si.base + (int64_t)a * si.stride] : T(0);
+            });
+        }
         if constexpr (FULL && MODE == M_STAGE23) {
             static_for<0, Q>([&](auto AA) {
                 constexpr int a = decltype(AA)::value;
@@ -507,11 +541,19 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK), (((MODE == M_STAGE23 || 
             // explicit modal filter (Sec. 2.2.3), all velocities per pass: the
             // node's values go to the Q planes, each pass is computed into
             // registers and written back (two barriers per pass)
-            static_for<0, Q>([&](auto AA) {
-                constexpr int a = decltype(AA)::value;
-                pl[a][p] = fq[a];
-            });
+            if (!slotted) {
+                static_for<0, Q>([&](auto AA) {
+                    constexpr int a = decltype(AA)::value;
+                    pl[a][p] = fq[a];
+                });
+            }
             __syncthreads();  // planes and sF visible
+            if (slotted) {
+                static_for<0, Q>([&](auto AA) {
+                    constexpr int a = decltype(AA)::value;
+                    fq[a] = pl[a][p];
+                });
+            }
             static_for<0, DIM>([&](auto MM) {
                 constexpr int m = decltype(MM)::value;
                 const int row = (m == 0) ? rowr : (m == 1) ? rows : rowt;
