@@ -143,7 +143,10 @@ int sel_workspace_bytes(const sel_mesh *mesh, const sel_params *p, size_t *bytes
  * sel_destroy; NULL makes the library allocate it. hip_stream is a
  * hipStream_t (NULL = default stream). The mesh may be destroyed after this
  * call. Errors: SEL_EINVAL (bad parameter or non-positive Jacobian),
- * SEL_ENOMEM, SEL_EDEVICE, SEL_EUNSUPPORTED. */
+ * SEL_ENOMEM, SEL_EDEVICE, SEL_EUNSUPPORTED (an order, lattice or storage
+ * form not built: D2Q9 N 2..10; D3Q19 and D3Q27 N 2..8; D3Q19 N 12, the
+ * highest Taylor-Green order of Sec. 3.4, which runs the continuous coupling
+ * without the closure and without sel_velocity_gradient). */
 int sel_init(const sel_mesh *mesh, const sel_params *p, const double *rho, const double *u,
              void *dev_ws, size_t ws_bytes, void *hip_stream, sel_sim **out);
 

@@ -22,7 +22,8 @@ extern "C" const char *sel_last_error(void) { return sel::g_err.c_str(); }
 
 extern "C" const char *sel_version(void)
 {
-    return "sel gfx950: dim 2 (D2Q9) N 2..10, dim 3 (D3Q27, D3Q19) N 2..8; FP64 and FP32 deviation storage";
+    return "sel gfx950: dim 2 (D2Q9) N 2..10, dim 3 (D3Q27, D3Q19) N 2..8 and D3Q19 N 12; FP64 and FP32 deviation "
+           "storage";
 }
 
 #define HIP_OK(call)                                                                   \
@@ -90,6 +91,12 @@ int check_params(const sel_mesh *m, const sel_params *p)
     }
     if (!sel::find_ops(m->dim, m->N, p->Q, p->precision)) {
         set_error("order N not compiled for this dim/Q/precision");
+        return SEL_EUNSUPPORTED;
+    }
+    // elements with more nodes than a workgroup has threads (3D, N >= 10) run
+    // the continuous coupling without the learned closure
+    if (m->np > 1024 && (m->dg || p->closure != nullptr)) {
+        set_error("the closure and the discontinuous coupling take one thread per element node: 3D orders with at most 1024 nodes (N <= 9)");
         return SEL_EUNSUPPORTED;
     }
     return SEL_OK;

@@ -13,6 +13,8 @@ const Ops *ops_d3q19_fp32(int N)
     case 6: return Impl<3, 6, 19, float, true>::ops();
     case 7: return Impl<3, 7, 19, float, true>::ops();
     case 8: return Impl<3, 8, 19, float, true>::ops();
+    // the Taylor-Green order of Sec. 3.4 (several nodes per thread)
+    case 12: return Impl<3, 12, 19, float, true>::ops();
     default: return nullptr;
     }
 }

@@ -13,6 +13,8 @@ const Ops *ops_d3q19_fp64(int N)
     case 6: return Impl<3, 6, 19, double, false>::ops();
     case 7: return Impl<3, 7, 19, double, false>::ops();
     case 8: return Impl<3, 8, 19, double, false>::ops();
+    // the Taylor-Green order of Sec. 3.4 (several nodes per thread)
+    case 12: return Impl<3, 12, 19, double, false>::ops();
     default: return nullptr;
     }
 }

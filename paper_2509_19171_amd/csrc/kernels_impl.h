@@ -418,6 +418,10 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK), (((MODE == M_STAGE23 || 
     __shared__ __attribute__((aligned(16))) T lds[LDS_N];
     T(*pl)[EPB * NP] = reinterpret_cast<T(*)[EPB * NP]>(lds);
     __shared__ T sF[ALLQ ? n1 * n1 : 1];
+    // FP32 first stage: D-hat in LDS as well (its rows are read after the
+    // collision, where global loads would add a memory latency)
+    constexpr bool SD = MODE == M_STAGE1 && FULL;
+    __shared__ T sD[SD ? n1 * n1 : 1];
 
     const int tid = threadIdx.x;
     const int le = tid / NP;
@@ -430,6 +434,10 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK), (((MODE == M_STAGE23 || 
     if constexpr (ALLQ) {
         if (filt)
             for (int q = tid; q < n1 * n1; q += GG::BLOCK) sF[q] = A.F[q];
+    }
+    if constexpr (SD) {
+        for (int q = tid; q < n1 * n1; q += GG::BLOCK) sD[q] = A.D[q];
+        if (!filt) __syncthreads();  // else the filter's first barrier makes it visible
     }
     const int i = p % n1;
     const int j = (p / n1) % n1;
@@ -491,6 +499,12 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK), (((MODE == M_STAGE23 || 
     // contiguous per velocity, boundary slots through their node group)
     constexpr bool SLOT = FF && FULL && EPB == 1 && MODE == M_STAGE1 && NB + NI == NP;
     bool slotted = false;
+    // the node's metric terms and inverse mass: with the slot loads they are
+    // issued together with the element's values, so that their latency is
+    // hidden behind the filter (else they are read after the collision)
+    T Gr[DIM][DIM];
+    T invw = 0;
+    bool have_metric = false;
     if constexpr (SLOT) {
         if (filt) {
             slotted = true;
@@ -512,6 +526,13 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK), (((MODE == M_STAGE23 || 
                 constexpr int a = decltype(AA)::value;
                 v[a] = src[a * stride];
             });
+#pragma unroll
+            for (int m = 0; m < DIM; ++m)
+#pragma unroll
+                for (int q = 0; q < DIM; ++q)
+                    Gr[m][q] = __builtin_nontemporal_load(A.Gm + (e * DIM * DIM + m * DIM + q) * NP + p);
+            if (inner) invw = A.invw[e * NI + pc];
+            have_metric = true;
             static_for<0, Q>([&](auto AA) {
                 constexpr int a = decltype(AA)::value;
                 pl[a][node] = v[a];
@@ -677,18 +698,19 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK), (((MODE == M_STAGE23 || 
     T Di[n1], Dj[n1], Dk[n1];
 #pragma unroll
     for (int c = 0; c < n1; ++c) {
-        Di[c] = A.D[i * n1 + c];
-        Dj[c] = A.D[j * n1 + c];
-        Dk[c] = (DIM == 3) ? A.D[k * n1 + c] : T(0);
+        const T *Dt = SD ? sD : A.D;
+        Di[c] = Dt[i * n1 + c];
+        Dj[c] = Dt[j * n1 + c];
+        Dk[c] = (DIM == 3) ? Dt[k * n1 + c] : T(0);
     }
-    T Gr[DIM][DIM];
+    if (!have_metric) {
 #pragma unroll
-    for (int m = 0; m < DIM; ++m)
+        for (int m = 0; m < DIM; ++m)
 #pragma unroll
-        for (int q = 0; q < DIM; ++q)
-            Gr[m][q] = valid ? __builtin_nontemporal_load(A.Gm + (e * DIM * DIM + m * DIM + q) * NP + p) : T(0);
-    T invw = 0;
-    if (MODE != M_LOCAL && valid && inner) invw = A.invw[e * NI + pc];
+            for (int q = 0; q < DIM; ++q)
+                Gr[m][q] = valid ? __builtin_nontemporal_load(A.Gm + (e * DIM * DIM + m * DIM + q) * NP + p) : T(0);
+        if (MODE != M_LOCAL && valid && inner) invw = A.invw[e * NI + pc];
+    }
 
     // wall faces through this node (flux bounce-back, Sec. 2.2.1): at most
     // one per reference direction m; 8 bits per direction hold the wall tag
@@ -1205,25 +1227,13 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK)) k_features(FeatArgs<T> A
 // ---------------------------------------------------------------- geometry --
 // Isoparametric geometry in FP64 (Sec. 2.2): dx/dr by D-hat on the node
 // coordinates, J = det, grad r_m = (a_{m+1} x a_{m+2}) / J with a_m = dx/dr_m
-// (2D: rotated tangents), wJ = w w w J, G_mk = wJ dr_m/dx_k.
+// (2D: rotated tangents), wJ = w w w J, G_mk = wJ dr_m/dx_k. Node p of
+// element e; coordinate q of element node c is sx[q * ld + off + c].
 template <int DIM, int N, typename T>
-__global__ void __launch_bounds__((Geo<DIM, N>::BLOCK))
-    k_geom(const double *xyz, const double *D, const double *w, double *wJ, double *Jo, T *Gm, int32_t *flag,
-           int64_t E, int64_t nblk)
+__device__ __forceinline__ void geom_node(const double *sx, int ld, int off, int p, int64_t e, const double *D,
+                                          const double *w, double *wJ, double *Jo, T *Gm, int32_t *flag)
 {
-    using GG = Geo<DIM, N>;
-    constexpr int n1 = GG::n1, NP = GG::NP, EPB = GG::EPB;
-    __shared__ double sx[DIM][EPB * NP];
-    const int tid = threadIdx.x;
-    const int le = tid / NP, p = tid - le * NP;
-    const int64_t eb = blockIdx.x;
-    if (eb >= nblk) return;
-    const int64_t e = eb * EPB + le;
-    const bool valid = e < E;
-#pragma unroll
-    for (int q = 0; q < DIM; ++q) sx[q][le * NP + p] = valid ? xyz[(e * NP + p) * DIM + q] : 0.0;
-    __syncthreads();
-    if (!valid) return;
+    constexpr int n1 = N + 1, NP = ipow_c(n1, DIM);
     const int idx[3] = {p % n1, (p / n1) % n1, DIM == 3 ? p / (n1 * n1) : 0};
     const int str[3] = {1, n1, n1 * n1};
     double a[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // a[m][q] = dx_q / dr_m
@@ -1231,7 +1241,7 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK))
         const int b0 = p - idx[m] * str[m];
         for (int c = 0; c < n1; ++c) {
             const double d = D[idx[m] * n1 + c];
-            for (int q = 0; q < DIM; ++q) a[m][q] += d * sx[q][le * NP + b0 + c * str[m]];
+            for (int q = 0; q < DIM; ++q) a[m][q] += d * sx[q * ld + off + b0 + c * str[m]];
         }
     }
     double J, gr[3][3];  // gr[m][q] = dr_m / dx_q
@@ -1261,6 +1271,27 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK))
     for (int m = 0; m < DIM; ++m)
         for (int q = 0; q < DIM; ++q) Gm[(e * DIM * DIM + m * DIM + q) * NP + p] = T(wj * gr[m][q]);
     if (!(J > 0.0)) atomicOr(flag, 1);
+}
+
+template <int DIM, int N, typename T>
+__global__ void __launch_bounds__((Geo<DIM, N>::BLOCK))
+    k_geom(const double *xyz, const double *D, const double *w, double *wJ, double *Jo, T *Gm, int32_t *flag,
+           int64_t E, int64_t nblk)
+{
+    using GG = Geo<DIM, N>;
+    constexpr int NP = GG::NP, EPB = GG::EPB;
+    __shared__ double sx[DIM][EPB * NP];
+    const int tid = threadIdx.x;
+    const int le = tid / NP, p = tid - le * NP;
+    const int64_t eb = blockIdx.x;
+    if (eb >= nblk) return;
+    const int64_t e = eb * EPB + le;
+    const bool valid = e < E;
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) sx[q][le * NP + p] = valid ? xyz[(e * NP + p) * DIM + q] : 0.0;
+    __syncthreads();
+    if (!valid) return;
+    geom_node<DIM, N, T>(&sx[0][0], EPB * NP, le * NP, p, e, D, w, wJ, Jo, Gm, flag);
 }
 
 // inverse lumped mass: interior nodes 1/wJ, boundary groups 1/sum of member wJ

@@ -1,6 +1,7 @@
 // Launch sequences of the SELBM kernels for one (dim, N, Q, storage) choice.
 #pragma once
 
+#include "kernels_big.h"
 #include "kernels_impl.h"
 #include "kernels_mfma.h"
 #include "ops.h"
@@ -22,6 +23,9 @@ struct Impl {
     static constexpr int NP = GG::NP, NI = GG::NI, NB = GG::NB, EPB = GG::EPB;
     // later-stage element kernel with matrix-core contractions (kernels_mfma.h)
     static constexpr bool kMfma = std::is_same<T, float>::value && DEV && DIM == 3 && N == 7;
+    // 3D orders whose element has more nodes than a workgroup has threads
+    // (kernels_big.h): several nodes per thread
+    static constexpr bool kBig = DIM == 3 && NP > 1024;
 
     static T *st(sel_sim *s, int i) { return static_cast<T *>(s->f[i]); }
     static int64_t nblk(sel_sim *s) { return (s->E + EPB - 1) / EPB; }
@@ -118,23 +122,32 @@ struct Impl {
         dim3 grid((unsigned)xcd_grid(A.nblk)), block(GG::BLOCK);
         hipEvent_t ev = nullptr;
         const int kind = (MODE == M_STAGE1) ? 0 : (MODE == M_STAGE23) ? 1 : 3;
-        if (int rc = tic(s, kind, ev)) return rc;
-        // element contributions under the discontinuous coupling carry the
-        // interface flux themselves; in the stages it is added by the
-        // assembly (k_group_split), where every element-boundary node is a group
-        bool dg = false;
-        if constexpr (MODE == M_LOCAL) {
-            dg = A.nbr != nullptr;
-            if (dg) {
-                hipLaunchKernelGGL((k_stage<DIM, N, Q, T, DEV, MODE, true>), grid, block, 0, s->stream, A);
+        if constexpr (kBig) {
+            if (A.nbr) {
+                set_error("the discontinuous coupling takes one thread per element node: 3D orders with at most 1024 nodes (N <= 9)");
+                return SEL_EUNSUPPORTED;
             }
-        }
-        if (!dg) {
-            // FP32 3D order 7, later stages: vector loads and matrix-core contractions
-            if constexpr (kMfma && MODE == M_STAGE23) {
-                hipLaunchKernelGGL((k_stage23_mf<Q>), grid, block, 0, s->stream, A);
-            } else {
-                hipLaunchKernelGGL((k_stage<DIM, N, Q, T, DEV, MODE>), grid, block, 0, s->stream, A);
+            if (int rc = tic(s, kind, ev)) return rc;
+            hipLaunchKernelGGL((k_stage_big<N, Q, T, DEV, MODE>), grid, dim3(BigGeo<N>::BLOCK), 0, s->stream, A);
+        } else {
+            if (int rc = tic(s, kind, ev)) return rc;
+            // element contributions under the discontinuous coupling carry the
+            // interface flux themselves; in the stages it is added by the
+            // assembly (k_group_split), where every element-boundary node is a group
+            bool dg = false;
+            if constexpr (MODE == M_LOCAL) {
+                dg = A.nbr != nullptr;
+                if (dg) {
+                    hipLaunchKernelGGL((k_stage<DIM, N, Q, T, DEV, MODE, true>), grid, block, 0, s->stream, A);
+                }
+            }
+            if (!dg) {
+                // FP32 3D order 7, later stages: vector loads and matrix-core contractions
+                if constexpr (kMfma && MODE == M_STAGE23) {
+                    hipLaunchKernelGGL((k_stage23_mf<Q>), grid, block, 0, s->stream, A);
+                } else {
+                    hipLaunchKernelGGL((k_stage<DIM, N, Q, T, DEV, MODE>), grid, block, 0, s->stream, A);
+                }
             }
         }
         SEL_LAUNCH_CHECK();
@@ -162,8 +175,13 @@ struct Impl {
     static int geometry(sel_sim *s)
     {
         const int64_t nb = nblk(s);
-        hipLaunchKernelGGL((k_geom<DIM, N, T>), dim3((unsigned)nb), dim3(GG::BLOCK), 0, s->stream, s->xyz,
-                           s->geoD, s->geoW, s->wJ, s->J, static_cast<T *>(s->Gm), s->flag, s->E, nb);
+        if constexpr (kBig) {
+            hipLaunchKernelGGL((k_geom_big<N, T>), dim3((unsigned)nb), dim3(BigGeo<N>::BLOCK), 0, s->stream, s->xyz,
+                               s->geoD, s->geoW, s->wJ, s->J, static_cast<T *>(s->Gm), s->flag, s->E);
+        } else {
+            hipLaunchKernelGGL((k_geom<DIM, N, T>), dim3((unsigned)nb), dim3(GG::BLOCK), 0, s->stream, s->xyz,
+                               s->geoD, s->geoW, s->wJ, s->J, static_cast<T *>(s->Gm), s->flag, s->E, nb);
+        }
         SEL_LAUNCH_CHECK();
         return SEL_OK;
     }
@@ -449,6 +467,16 @@ struct Impl {
     static int grad_row(sel_sim *s, int c, double *d_out) { return feat(s, nullptr, 0, 0, d_out, c); }
 
     static int feat(sel_sim *s, float *X, int owner_out, int filter, double *grad, int row)
+    {
+        if constexpr (kBig) {
+            set_error("closure features and velocity gradients take one thread per element node: 3D orders with at most 1024 nodes (N <= 9)");
+            return SEL_EUNSUPPORTED;
+        } else {
+            return feat_launch(s, X, owner_out, filter, grad, row);
+        }
+    }
+
+    static int feat_launch(sel_sim *s, float *X, int owner_out, int filter, double *grad, int row)
     {
         FeatArgs<T> F{};
         F.grad = grad;

@@ -178,14 +178,29 @@ def test_mesh_ingest_rejects_shared_wall_face():
     assert ex.value.code == sel.SEL_EINVAL and "wall face" in str(ex.value)
 
 
-def test_order_beyond_one_thread_per_node_is_unsupported():
-    """3D orders are built up to N = 8 (one thread per node, at most 1024
-    nodes per workgroup); N = 12 (2197 nodes, one of the paper's Taylor-Green
-    orders) is refused with SEL_EUNSUPPORTED before any device call."""
-    c = I.case_tgv3d(nel=1, N=12, Q=19, steps=0)
-    sm = sel.Mesh.from_inputs(c.mesh)
-    with pytest.raises(sel.SelError) as ex:
-        sm.workspace_bytes(sel.params_from_case(c, "fp32dev"))
-    assert ex.value.code == sel.SEL_EUNSUPPORTED
+def test_compiled_orders_and_refusals():
+    """3D orders N 2..8 run one thread per element node; D3Q19 also at
+    N = 12 (2197 nodes, the paper's highest Taylor-Green order), with several
+    nodes per thread. Other orders and lattices, and the closure at N = 12,
+    are refused with SEL_EUNSUPPORTED before any device call."""
+    c12 = I.case_tgv3d(nel=1, N=12, Q=19, steps=0)
+    m12 = sel.Mesh.from_inputs(c12.mesh)
+    for prec in ("fp64", "fp32dev"):
+        assert m12.workspace_bytes(sel.params_from_case(c12, prec)) > 0
     c8 = I.case_tgv3d(nel=1, N=8, Q=19, steps=0)
     assert sel.Mesh.from_inputs(c8.mesh).workspace_bytes(sel.params_from_case(c8, "fp32dev")) > 0
+    refused = [(I.case_tgv3d(nel=1, N=12, Q=27, steps=0), None), (I.case_tgv3d(nel=1, N=10, Q=19, steps=0), None),
+               (c12, np.zeros(sel.closure_len(), dtype=np.float32))]
+    for c, blob in refused:
+        p = sel.params_from_case(c, "fp32dev")
+        if blob is not None:
+            p._closure_blob = blob
+            p.closure = blob.ctypes.data
+            p.closure_len = blob.size
+        with pytest.raises(sel.SelError) as ex:
+            sel.Mesh.from_inputs(c.mesh).workspace_bytes(p)
+        assert ex.value.code == sel.SEL_EUNSUPPORTED, (c.N, c.Q)
+    c12b = I.case_tgv3d(nel=2, N=12, Q=19, steps=0)  # two elements per periodic direction
+    with pytest.raises(sel.SelError) as ex:
+        sel.Mesh.from_inputs(c12b.mesh, "dg").workspace_bytes(sel.params_from_case(c12b, "fp64"))
+    assert ex.value.code == sel.SEL_EUNSUPPORTED

@@ -1,0 +1,179 @@
+"""The paper's highest Taylor-Green order (Sec. 3.4: D3Q19 at N = 12, 2197
+nodes per element, more than one workgroup has threads) against the FP64
+oracle: geometry, each operator, whole runs with the filter, curved FBB walls
+with a moving wall, a body force and a per-node force, and the integrals.
+
+Tolerances (normwise relative error, as in the other parity tests): FP64
+1e-12 on f, rho, u and the geometry; FP32 deviation storage 1e-5 on rho and u
+after 200 steps, and on single operators 2e-6 x (12/8)^2 = 4.5e-6: the bound
+used up to N = 8 scaled by the growth of the collocation derivative's
+conditioning (~N^2) from N = 8 to 12."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from conftest import nerr
+from paper_2509_19171_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def uerr(u, uref):
+    return float(np.abs(u - uref).max() / max(np.abs(uref).max(), 0.01))
+
+
+def _warp(x):  # periodic in x and z, flat walls at y = 0, 1
+    out = x.copy()
+    out[..., 0] += 0.02 * np.sin(2 * math.pi * x[..., 2] / 1.5)
+    out[..., 1] += 0.02 * np.sin(math.pi * x[..., 1]) * np.sin(2 * math.pi * x[..., 0])
+    out[..., 2] += 0.02 * np.sin(2 * math.pi * x[..., 0])
+    return out
+
+
+def _cases():
+    out = {}
+    # Ma = 0.1 / sqrt(3), Re = 1600 as in Sec. 3.4
+    out["tgv3d_q19_N12"] = I.case_tgv3d(nel=2, N=12, Q=19, Re=1600.0, Ma=0.1 / math.sqrt(3.0), steps=0,
+                                        filt="quad")
+    # curved walls in y (the top one moving), a body force, one element
+    # across z (periodic onto itself)
+    m = I.box_mesh(3, 12, (2, 2, 1), (0, 0, 0), (1, 1, 1.5), (True, False, True), wall_tags={1: (1, 2)},
+                   wall_u=[[0, 0, 0], [0.02, 0, 0.01]], warp=_warp)
+    r, u = I.rest_fields(m.xyz)
+    c = I.Case("box3d_q19_N12", m, 19, 1.0, 0.01, I.stable_dt(m), r, u, 0, g=(0.0, 0.0, 1e-3),
+               filter="quad", filter_kc=2, filter_amp=0.1)
+    c.rho, c.u = I.random_state(c, seed=12, amp=0.01)
+    out["box3d_q19_walls_N12"] = c
+    return out
+
+
+CASES = _cases()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu_ready():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    from paper_2509_19171_amd import sel
+
+    sel.load()
+    yield
+
+
+def _random_f(case, seed=3, amp=1e-2):
+    """A continuous (per global node) perturbed equilibrium-like state."""
+    import oracle
+
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ng = int(case.gid.max()) + 1
+    _, t, _ = oracle.lattice(case.dim, case.Q)
+    base = t[None, :] * (1.0 + amp * rng.standard_normal((ng, case.Q)))
+    return base[case.gid].transpose(0, 2, 1).copy()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_high_order_geometry(name):
+    import oracle
+    from paper_2509_19171_amd import sel
+
+    c = CASES[name]
+    say(f"geometry {name}")
+    g = sel.from_case(c, "fp64")
+    wJ, J = g.geometry()
+    owJ, _, oJ = oracle.from_case(c).geometry()
+    assert nerr(wJ, owJ) < 1e-12 and nerr(J, oJ) < 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32dev", 4.5e-6)])
+@pytest.mark.parametrize("op", ["rhs_local", "rhs", "collide", "filter"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_high_order_operator_parity(name, op, prec, tol):
+    import oracle
+    from paper_2509_19171_amd import sel
+
+    c = CASES[name]
+    say(f"operator {op} {prec} {name}")
+    g = sel.from_case(c, prec)
+    o = oracle.from_case(c)
+    f = _random_f(c)
+    got = g.apply(op, f)
+    ref = {"rhs_local": o.rhs_local, "rhs": o.rhs, "collide": o.collide, "filter": o.filter}[op](f)
+    if op in ("rhs_local", "rhs"):
+        err = np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300)
+    else:
+        err = nerr(got, ref)
+    say(f"  error {err:.2e}")
+    assert err < tol, err
+
+
+@pytest.mark.parametrize("prec,steps", [("fp64", 20), ("fp32dev", 200)])
+@pytest.mark.parametrize("name", list(CASES))
+def test_high_order_step_parity(name, prec, steps):
+    import oracle
+    from paper_2509_19171_amd import sel
+
+    c = CASES[name]
+    say(f"steps {prec} {name} x{steps}")
+    g = sel.from_case(c, prec)
+    o = oracle.from_case(c)
+    g.step(steps)
+    o.step(steps)
+    rho, u = g.moments()
+    orho, ou = o.moments()
+    er = nerr(rho, orho)
+    eu = uerr(u, ou) if prec == "fp64" else nerr(u, ou)
+    say(f"  rho {er:.2e} u {eu:.2e}")
+    if prec == "fp64":
+        assert er < 1e-12 and eu < 1e-12
+        assert nerr(g.get_f(), o.get_f()) < 1e-12
+        red, ored = g.reduce(), o.reduce()
+        assert abs(red[0] - ored[0]) < 1e-12 * abs(ored[0])
+        assert abs(red[4] - ored[4]) < 1e-11 * abs(ored[4])  # kinetic energy
+        assert red[-1] == 0
+    else:
+        assert er < 1e-5 and eu < 1e-5
+
+
+def test_high_order_node_force_parity():
+    """A per-node force field (the first stage then collides and streams in
+    two launches) on the walled case, FP64 and FP32 deviation storage."""
+    import oracle
+    from paper_2509_19171_amd import sel
+
+    c = CASES["box3d_q19_walls_N12"]
+    rng = np.random.Generator(np.random.PCG64(21))
+    F = 1e-3 * rng.standard_normal((int(c.gid.max()) + 1, 3))[c.gid]
+    o = oracle.from_case(c)
+    o.set_force(F)
+    o.step(20)
+    orho, ou = o.moments()
+    for prec, tol in (("fp64", 1e-12), ("fp32dev", 1e-5)):
+        say(f"node force {prec}")
+        g = sel.from_case(c, prec)
+        g.set_force(F)
+        g.step(20)
+        rho, u = g.moments()
+        er = nerr(rho, orho)
+        eu = uerr(u, ou) if prec == "fp64" else nerr(u, ou)
+        say(f"  rho {er:.2e} u {eu:.2e}")
+        assert er < tol and eu < tol, prec
+
+
+def test_high_order_gradient_is_refused():
+    """The velocity-gradient diagnostic (one thread per node) is built up to
+    N = 9 in 3D (one thread per element node): at N = 12 it returns
+    SEL_EUNSUPPORTED."""
+    from paper_2509_19171_amd import sel
+
+    g = sel.from_case(CASES["tgv3d_q19_N12"], "fp64")
+    with pytest.raises(sel.SelError) as ex:
+        g.velocity_gradient()
+    assert ex.value.code == sel.SEL_EUNSUPPORTED
