@@ -7,8 +7,9 @@ node-velocities), Re = 1600, Ma = 0.1, the paper's quadratic filter
 (gamma = 0.1, k_c = 2), SSPRK3, inputs resident in HBM. The headline form is
 FP32 deviation storage; the FP64, learned-closure and discontinuous forms are
 timed beside it, and the other workload shapes (2D Taylor-Green, double shear
-layer, curved channel, O-grid pipe at N = 7 and its N = 5 closure variant)
-get throughput lines of their own.
+layer, curved channel, the paper's D3Q19 Taylor-Green runs at N = 8 and 12,
+O-grid pipe at N = 7 and its N = 5 closure variant) get throughput lines of
+their own.
 
 Prints ONE JSON line. ``value`` is node-velocity updates per second (1e9,
 local nodes E (N+1)^3 Q per step). ``roofline`` prices one later SSPRK stage
@@ -27,6 +28,7 @@ import argparse
 import dataclasses
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -269,6 +271,17 @@ def other_configs(torch, steps):
                                I.case_double_shear(), prec, k, 10, torch, hbm=False))
         out.append(time_config("2D curved Poiseuille channel, D2Q9, 16x8 quads, N=7, FBB walls",
                                I.case_poiseuille(curved=True), prec, k, 10, torch, hbm=False))
+    # the paper's 3D Taylor-Green runs (Sec. 3.4): D3Q19, 16^3 hexes, N = 8 and
+    # 12 (N = 12 takes the several-nodes-per-thread kernels)
+    kt = max(10, steps // 20)
+    for N in (8, 12):
+        print(f"[bench] timing the Taylor-Green vortex at N = {N}", file=sys.stderr, flush=True)
+        tgv = I.case_tgv3d(nel=16, N=N, Q=19, Re=1600.0, Ma=0.1 / math.sqrt(3.0), steps=0, filt="quad")
+        for prec in ("fp32dev", "fp64"):
+            out.append(time_config(f"3D Taylor-Green vortex, D3Q19, 16^3 hexes, N={N}, Re 1600", tgv, prec, kt, 3,
+                                   torch))
+        del tgv
+        torch.cuda.empty_cache()
     print("[bench] timing the O-grid pipe", file=sys.stderr, flush=True)
     pipe = I.case_pipe()
     kp = max(10, steps // 10)
