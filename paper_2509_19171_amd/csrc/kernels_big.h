@@ -178,16 +178,51 @@ __global__ void __launch_bounds__(BigGeo<N>::BLOCK) k_stage_big(StageArgs<T> A)
     for (int r = 0; r < R; ++r)
         invw[r] = (MODE != M_LOCAL && ok[r] && pcv[r] >= 0) ? A.invw[e * NI + pcv[r]] : T(0);
 
+    // FP32: the metric terms of the thread's nodes are read once, and the next
+    // velocity's operand and f* are loaded while this one streams (in FP64
+    // both made the compiler spill the values it holds: slower)
+    constexpr bool PF = DIF;
+    T Gk[PF ? R : 1][DIM][DIM];
+    T vn[PF ? R : 1], f0n[PF ? R : 1];
+    auto fetch = [&](auto BB) {
+        constexpr int b = decltype(BB)::value;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if constexpr (S1) vn[r] = fq[r][b];
+            else vn[r] = ok[r] ? A.op[si[r].base + (int64_t)b * si[r].stride] : T(0);
+            if constexpr (MODE == M_STAGE23)
+                f0n[r] = (ok[r] && pcv[r] >= 0) ? A.f0in[si[r].base + (int64_t)b * si[r].stride] : T(0);
+            else f0n[r] = vn[r];
+        }
+    };
+    if constexpr (PF) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int m = 0; m < DIM; ++m)
+#pragma unroll
+                for (int q = 0; q < DIM; ++q)
+                    Gk[r][m][q] = ok[r] ? A.Gm[(e * DIM * DIM + m * DIM + q) * NP + pn[r]] : T(0);
+        fetch(std::integral_constant<int, 0>{});
+    }
+
     // streaming operator (Sec. 2.2), one velocity plane at a time
     static_for<0, Q>([&](auto AA) {
         constexpr int a = decltype(AA)::value;
         constexpr bool rest = lat_e<DIM, Q>(a, 0) == 0 && lat_e<DIM, Q>(a, 1) == 0 && lat_e<DIM, Q>(a, 2) == 0;
-        T v[R];
+        T v[R], f0[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            if constexpr (S1) v[r] = fq[r][a];
-            else v[r] = ok[r] ? A.op[si[r].base + (int64_t)a * si[r].stride] : T(0);
+            if constexpr (PF) {
+                v[r] = vn[r];
+                f0[r] = f0n[r];
+            } else if constexpr (S1) {
+                v[r] = fq[r][a];
+            } else {
+                v[r] = ok[r] ? A.op[si[r].base + (int64_t)a * si[r].stride] : T(0);
+            }
         }
+        if constexpr (PF && a + 1 < Q) fetch(std::integral_constant<int, a + 1>{});
         // the rest velocity does not stream: no plane
         if constexpr (!rest) {
 #pragma unroll
@@ -212,7 +247,10 @@ __global__ void __launch_bounds__(BigGeo<N>::BLOCK) k_stage_big(StageArgs<T> A)
 #pragma unroll
                 for (int m = 0; m < DIM; ++m)
 #pragma unroll
-                    for (int q = 0; q < DIM; ++q) Gr[m][q] = A.Gm[(e * DIM * DIM + m * DIM + q) * NP + p];
+                    for (int q = 0; q < DIM; ++q) {
+                        if constexpr (PF) Gr[m][q] = Gk[r][m][q];
+                        else Gr[m][q] = A.Gm[(e * DIM * DIM + m * DIM + q) * NP + p];
+                    }
                 rt = stream_volume<DIM, N, Q, a, DIF>(pl[0], v[r], Di, Dj, Dk, Gr, n1 * j + n1 * n1 * k,
                                                       i + n1 * n1 * k, i + n1 * j);
                 if (wcode[r]) {
@@ -228,6 +266,7 @@ __global__ void __launch_bounds__(BigGeo<N>::BLOCK) k_stage_big(StageArgs<T> A)
             } else if (pcv[r] >= 0) {
                 T f0v;
                 if constexpr (S1) f0v = v[r];
+                else if constexpr (PF) f0v = f0[r];
                 else f0v = A.f0in[si[r].base + (int64_t)a * si[r].stride];
                 const T L = rt * invw[r] + A.fsc[a] * rho[r];
                 A.out[si[r].base + (int64_t)a * si[r].stride] = rk_combine(A.ca, A.cb, A.cc, f0v, v[r], L, A.incr);

@@ -500,11 +500,14 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK), (((MODE == M_STAGE23 || 
     constexpr bool SLOT = FF && FULL && EPB == 1 && MODE == M_STAGE1 && NB + NI == NP;
     bool slotted = false;
     // the node's metric terms and inverse mass: with the slot loads they are
-    // issued together with the element's values, so that their latency is
-    // hidden behind the filter (else they are read after the collision)
+    // issued together with the element's values and parked in LDS (18 KB at
+    // N = 7; two elements per CU still fit), so that their latency is hidden
+    // behind the filter and they hold no registers through it (else they are
+    // read after the collision)
     T Gr[DIM][DIM];
     T invw = 0;
     bool have_metric = false;
+    __shared__ T sG[SLOT ? (DIM * DIM + 1) * NP : 1];
     if constexpr (SLOT) {
         if (filt) {
             slotted = true;
@@ -526,17 +529,18 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK), (((MODE == M_STAGE23 || 
                 constexpr int a = decltype(AA)::value;
                 v[a] = src[a * stride];
             });
+            T gt[DIM * DIM];
 #pragma unroll
-            for (int m = 0; m < DIM; ++m)
-#pragma unroll
-                for (int q = 0; q < DIM; ++q)
-                    Gr[m][q] = __builtin_nontemporal_load(A.Gm + (e * DIM * DIM + m * DIM + q) * NP + p);
-            if (inner) invw = A.invw[e * NI + pc];
+            for (int m = 0; m < DIM * DIM; ++m) gt[m] = __builtin_nontemporal_load(A.Gm + (e * DIM * DIM + m) * NP + p);
+            const T iw = inner ? A.invw[e * NI + pc] : T(0);
             have_metric = true;
             static_for<0, Q>([&](auto AA) {
                 constexpr int a = decltype(AA)::value;
                 pl[a][node] = v[a];
             });
+#pragma unroll
+            for (int m = 0; m < DIM * DIM; ++m) sG[m * NP + p] = gt[m];
+            sG[DIM * DIM * NP + p] = iw;
         }
     }
     if constexpr (ALLQ || FULL) {
@@ -703,7 +707,13 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK), (((MODE == M_STAGE23 || 
         Dj[c] = Dt[j * n1 + c];
         Dk[c] = (DIM == 3) ? Dt[k * n1 + c] : T(0);
     }
-    if (!have_metric) {
+    if (have_metric) {
+#pragma unroll
+        for (int m = 0; m < DIM; ++m)
+#pragma unroll
+            for (int q = 0; q < DIM; ++q) Gr[m][q] = sG[(m * DIM + q) * NP + p];
+        invw = sG[DIM * DIM * NP + p];
+    } else {
 #pragma unroll
         for (int m = 0; m < DIM; ++m)
 #pragma unroll

@@ -69,7 +69,7 @@ def _poly(x, deg):
     return f, grad
 
 
-@pytest.mark.parametrize("dim,Q,N", [(2, 9, 3), (2, 9, 6), (3, 27, 3), (3, 19, 4)])
+@pytest.mark.parametrize("dim,Q,N", [(2, 9, 3), (2, 9, 6), (3, 27, 3), (3, 19, 4), (3, 19, 12)])
 def test_streaming_operator_exact_on_polynomials(oracle_mod, dim, Q, N):
     """-M^-1 C_a f = -e_a . grad f exactly for polynomials of degree <= N on
     affine elements, at every node, after assembly."""
