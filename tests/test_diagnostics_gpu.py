@@ -123,6 +123,40 @@ def test_pipe_wall_shear_laminar():
     assert abs(tau - 4 * c.meta["ub"]) < 1e-3 * 4 * c.meta["ub"]
 
 
+def test_pipe_wall_units_laminar():
+    """Wall units (Sec. 3.5) of the laminar profile u_z = 2 u_b (1 - r^2/R^2)
+    on the curved O-grid (no body force, so the state's velocity is the
+    profile itself): u_tau from the wall shear stress against
+    sqrt(nu 4 u_b / R) to 5e-4 (the wall gradient is good to 1e-3), each bin's
+    mean axial velocity u+ u_tau against the lumped-mass average of the exact
+    profile over the bin's nodes to 1e-10 of u_b, and y+ = (R - r) u_tau / nu
+    at the bin centres."""
+    import dataclasses
+
+    from paper_2509_19171_amd import sel
+    from paper_2509_19171_amd import wallunits as W
+
+    c = dataclasses.replace(I.case_pipe(N=6, nsq=2, nrad=2, nax=4, L=2.0, pert=0.0, filt=None), g=(0.0, 0.0, 0.0))
+    R, ub, nb = c.meta["R"], c.meta["ub"], 7
+    g = sel.from_case(c, "fp64")
+    prof = W.WallProfile((0, 0, 0), (0, 0, 1), R, nb, c.rho0, c.nu)
+    prof.add(g, c.mesh.xyz)
+    yp, up, ut = prof.result()
+    ut_ref = math.sqrt(c.nu * 4 * ub / R)
+    say(f"  u_tau {ut:.6e} (exact {ut_ref:.6e}); u+ {np.round(up, 3)}")
+    assert abs(ut - ut_ref) < 5e-4 * ut_ref
+    wJ, _ = g.geometry()
+    x, y = c.mesh.xyz[..., 0], c.mesh.xyz[..., 1]
+    r = np.sqrt(x * x + y * y)  # the library's binning: sqrt(r^2) / rmax * nbins
+    b = np.floor(r / R * nb).astype(int)
+    uex = 2 * ub * (1 - (r / R) ** 2)
+    ref = np.array([(wJ * uex)[b == k].sum() / wJ[b == k].sum() for k in range(nb) if (b == k).any()])
+    assert up.shape == ref.shape
+    assert np.abs(up * ut - ref).max() < 1e-10 * ub
+    centres = (np.arange(nb) + 0.5) * R / nb
+    np.testing.assert_allclose(yp, (R - centres[[k for k in range(nb) if (b == k).any()]]) * ut / c.nu, rtol=1e-14)
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32dev", 1e-5)])
 def test_radial_profile_parity(prec, tol):
     """sel_radial_profile (the pipe's averaged axial velocity profile, Sec.
