@@ -494,10 +494,11 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK), (((MODE == M_STAGE23 || 
             });
         }
     };
-    // first stage with the filter, one element per workgroup: the element's
-    // values go straight to the planes, one slot per thread (interior slots
-    // contiguous per velocity, boundary slots through their node group)
-    constexpr bool SLOT = FF && FULL && EPB == 1 && MODE == M_STAGE1 && NB + NI == NP;
+    // first stage with the filter, and the later stages (FP32, one element
+    // per workgroup): the element's values go straight to the planes, one slot
+    // per thread (interior slots contiguous per velocity, boundary slots
+    // through their node group)
+    constexpr bool SLOT = FULL && EPB == 1 && NB + NI == NP && ((MODE == M_STAGE1 && FF) || MODE == M_STAGE23);
     bool slotted = false;
     // the node's metric terms and inverse mass: with the slot loads they are
     // issued together with the element's values and parked in LDS (18 KB at
@@ -509,7 +510,7 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK), (((MODE == M_STAGE23 || 
     bool have_metric = false;
     __shared__ T sG[SLOT ? (DIM * DIM + 1) * NP : 1];
     if constexpr (SLOT) {
-        if (filt) {
+        if (MODE == M_STAGE23 || filt) {
             slotted = true;
             const T *src;
             int node, stride;
@@ -795,13 +796,22 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK), (((MODE == M_STAGE23 || 
     };
 
     if constexpr (FULL) {
-        // the filter passes of the first stage used the same LDS
-        if constexpr (ALLQ) __syncthreads();
-        static_for<0, Q>([&](auto AA) {
-            constexpr int a = decltype(AA)::value;
-            pl[a][p] = fq[a];
-        });
-        __syncthreads();
+        if (MODE == M_STAGE23 && slotted) {
+            // the planes already hold the operand (filled slot by slot)
+            __syncthreads();
+            static_for<0, Q>([&](auto AA) {
+                constexpr int a = decltype(AA)::value;
+                fq[a] = pl[a][p];
+            });
+        } else {
+            // the filter passes of the first stage used the same LDS
+            if constexpr (ALLQ) __syncthreads();
+            static_for<0, Q>([&](auto AA) {
+                constexpr int a = decltype(AA)::value;
+                pl[a][p] = fq[a];
+            });
+            __syncthreads();
+        }
         static_for<0, Q>([&](auto AA) {
             constexpr int a = decltype(AA)::value;
             T f0v;
