@@ -853,9 +853,22 @@ __global__ void __launch_bounds__((Geo<DIM, N>::BLOCK), (((MODE == M_STAGE23 || 
                 }
             }
             const int32_t *pm = A.posmap + e * NB;
-            for (int q = tid; q < Q * NB; q += GG::BLOCK) {
-                const int a = q / NB, b = q - a * NB;
-                A.rtb[(int64_t)a * A.plane + pm[b]] = lds[a * NP + NI + b];
+            if constexpr (MODE == M_STAGE23) {
+                // later stages: one slot per thread (its rank-plane position
+                // read once); the rest velocity's contributions are zero and
+                // the assembly does not read them
+                if (tid < NB) {
+                    T *dst = A.rtb + pm[tid];
+                    static_for<1, Q>([&](auto AA) {
+                        constexpr int a = decltype(AA)::value;
+                        dst[(int64_t)a * A.plane] = lds[a * NP + NI + tid];
+                    });
+                }
+            } else {
+                for (int q = tid; q < Q * NB; q += GG::BLOCK) {
+                    const int a = q / NB, b = q - a * NB;
+                    A.rtb[(int64_t)a * A.plane + pm[b]] = lds[a * NP + NI + b];
+                }
             }
         }
     } else {
